@@ -1,0 +1,98 @@
+/*
+ * liborbgrand -- basic Ordered Reliability Bits GRAND on AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes, no framework types.
+ *
+ * Method: Duffy, An, Medard, "Ordered Reliability Bits Guessing Random
+ * Additive Noise Decoding" (arXiv 2202.13951).
+ *
+ * Conventions shared by every entry point
+ *   - Status: 0 (ORBG_OK) on success, a negative ORBG_E* code otherwise;
+ *     orbg_last_error() then returns a message for the calling thread.
+ *   - Parity-check matrix H: HOST pointer, (n - k) rows by n columns,
+ *     row-major, one byte per entry, each 0 or 1.  1 <= n <= 1024 and
+ *     1 <= n - k <= 64.  The library copies and packs it (column i becomes a
+ *     64-bit word whose bit r is H[r][i]) into a device cache keyed by its
+ *     contents; the caller keeps ownership of H.  If H has rank below n - k the
+ *     decoder decodes the code H defines (k only sizes H).
+ *   - LLRs: DEVICE pointer, `batch` rows of n FP32 values, row-major, the log
+ *     ratio log f(Y|1)/f(Y|0) of Sec. III-A (positive means bit 1).  Values are
+ *     not checked: NaN and -0 decide bit 0 and sort by their IEEE bits.
+ *   - Outputs: DEVICE pointers owned by the caller: codeword (batch rows of n
+ *     bytes, 0/1, in received order), queries (one u64 per block: code-book
+ *     queries made, the empty pattern counting as the first), abandoned (one
+ *     byte per block: 1 if the budget ran out, then queries == budget and the
+ *     codeword row is the hard decision).
+ *   - budget: the largest number of queries per block, 1 <= budget <= 2^28.
+ *   - stream: a hipStream_t (NULL = the default stream).  Decodes are
+ *     asynchronous on that stream.  The first call for a new H, or for a new
+ *     (n, budget) query schedule, allocates device memory and synchronises the
+ *     stream once; later calls do neither.
+ *   - Calls from several host threads are safe; calls on different streams
+ *     are independent.
+ */
+#ifndef ORBGRAND_H
+#define ORBGRAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORBG_OK 0
+#define ORBG_EINVAL (-1)       /* an argument is out of range or a pointer is NULL */
+#define ORBG_ENOMEM (-2)       /* a device allocation failed */
+#define ORBG_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+
+/*
+ * Plain basic-ORBGRAND decode of `batch` blocks of one linear code.
+ *
+ * Follows Algorithm 1 (GRAND: test putative noise patterns from most to least
+ * likely; the first y XOR z in the code-book is the decoding) with the basic
+ * ORBGRAND pattern order: bits ranked by increasing reliability |LLR| (ties by
+ * lower received index), patterns taken by increasing logistic weight (the sum
+ * of the flipped ranks, Sec. III-B eq. (lw)), inside one logistic weight by
+ * increasing Hamming weight (eq. (fractionation)), inside one (logistic,
+ * Hamming) weight in the order of the Landslide generator (Sec. III-C,
+ * Algorithm 2).  Membership is the parity-check product H x = 0 (Sec. I).  A
+ * block is abandoned once `budget` queries find no member (Sec. IV-A).
+ */
+int orbg_decode(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                int64_t batch, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                void* stream);
+
+/*
+ * Decode with a per-block reordering of the first 4096 patterns.
+ *
+ * The basic-ORBGRAND order (as in orbg_decode) is cut into batches of 64
+ * consecutive patterns; batch b holds global indices [64b, 64b + 64).
+ * `order` is a DEVICE array of batch x 64 bytes; row j must be a permutation
+ * of 0..63 and gives the order in which block j tests batches 0..63 (ascending
+ * index inside a batch).  The plain order then continues from index 4096.
+ * `queries` counts positions in this sequence; budget and abandonment are as
+ * in orbg_decode.  Requires n >= 12.  Rows that are not permutations give
+ * undefined results (the library does not read device memory to check them).
+ * This is the decode step of the learned proposal: ORBGRAND's own order stays
+ * the fallback after the reordered prefix.
+ */
+int orbg_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                        int64_t batch, const uint8_t* order, uint8_t* codeword,
+                        uint64_t* queries, uint8_t* abandoned, void* stream);
+
+/*
+ * Copies the first `count` entries of the library's basic-ORBGRAND query
+ * schedule for length n into the HOST buffer `out` (count x 16 bytes): entry g
+ * lists the 1-based reliability ranks flipped by query g + 1 in increasing
+ * order, padded with zeros (Sec. III-B/C order as described for orbg_decode).
+ * 1 <= count <= 2^28 and count <= 2^n.  Synchronises `stream`.
+ */
+int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream);
+
+/* Message describing the calling thread's last non-OK status ("" if none). */
+const char* orbg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORBGRAND_H */

@@ -91,6 +91,19 @@ def order_prefix(n: int, count: int) -> list[tuple[int, ...]]:
     return [tuple(int(x) for x in out[g, :wout[g]]) for g in range(got)]
 
 
+def order_prefix_array(n: int, count: int) -> np.ndarray:
+    """First `count` patterns as an int32 [count, 16] array of ranks (zero padded)."""
+    L = lib()
+    out = np.zeros((count, WIDTH), dtype=np.int32)
+    wout = np.zeros(count, dtype=np.int32)
+    got = L.oracle_order_prefix(n, count, WIDTH,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                wout.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if got < 0:
+        raise ValueError("pattern wider than the row width")
+    return out[:got]
+
+
 def decode(H: np.ndarray, llr: np.ndarray, budget: int, threads: int = 1):
     """Plain ORBGRAND on every row of llr.  Returns (codeword u8[N,n], queries u64[N],
     abandoned u8[N])."""

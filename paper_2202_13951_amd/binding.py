@@ -1,0 +1,120 @@
+"""ctypes binding of liborbgrand (argument marshalling only).
+
+Every computation happens in the HIP library; torch supplies device memory and
+the current stream.  Importing this module never falls back to anything: if the
+library is missing, load() raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liborbgrand.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "orbgrand.h")
+
+ORBG_OK = 0
+_lib = None
+
+
+class OrbgError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load liborbgrand.so (built in-tree by build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"liborbgrand.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i64, ci = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int
+    L.orbg_decode.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp]
+    L.orbg_decode.restype = ci
+    L.orbg_decode_ordered.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp, vp]
+    L.orbg_decode_ordered.restype = ci
+    L.orbg_schedule_export.argtypes = [ci, u64, vp, vp]
+    L.orbg_schedule_export.restype = ci
+    L.orbg_last_error.argtypes = []
+    L.orbg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def header_symbols() -> list[str]:
+    """Function names the public header declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(orbg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _check(fn: str, rc: int):
+    if rc != ORBG_OK:
+        raise OrbgError(fn, rc, load().orbg_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host_H(H) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(H), dtype=np.uint8)
+
+
+def _outputs(N, n, device, out):
+    import torch
+    if out is not None:
+        return out
+    return (torch.empty((N, n), dtype=torch.uint8, device=device),
+            torch.empty((N,), dtype=torch.int64, device=device),
+            torch.empty((N,), dtype=torch.uint8, device=device))
+
+
+def orbg_decode(H, llr, budget: int, out=None, stream=None):
+    """Plain basic-ORBGRAND decode.  H: host (n-k) x n 0/1 array; llr: CUDA float32
+    tensor [N, n].  Returns (codeword u8 [N, n], queries int64 [N], abandoned u8 [N])
+    on the same device (queries holds the u64 counts)."""
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    assert llr.is_cuda and llr.dtype.__str__() == "torch.float32" and llr.is_contiguous()
+    assert llr.dim() == 2 and llr.shape[1] == n
+    N = llr.shape[0]
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    rc = load().orbg_decode(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
+                            int(budget), N, ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                            ctypes.c_void_p(ab.data_ptr()), _stream_ptr(stream))
+    _check("orbg_decode", rc)
+    return cw, q, ab
+
+
+def orbg_decode_ordered(H, llr, budget: int, order, out=None, stream=None):
+    """Decode with a per-block order of the first 64 batches; order: CUDA uint8 [N, 64]."""
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    assert llr.is_cuda and llr.is_contiguous() and llr.dim() == 2 and llr.shape[1] == n
+    N = llr.shape[0]
+    assert order.is_cuda and order.is_contiguous() and tuple(order.shape) == (N, 64)
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    rc = load().orbg_decode_ordered(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n,
+                                    n - m, int(budget), N, ctypes.c_void_p(order.data_ptr()),
+                                    ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                    ctypes.c_void_p(ab.data_ptr()), _stream_ptr(stream))
+    _check("orbg_decode_ordered", rc)
+    return cw, q, ab
+
+
+def orbg_schedule_export(n: int, count: int, stream=None) -> np.ndarray:
+    """The first `count` schedule entries for length n: uint8 [count, 16] of ranks."""
+    out = np.zeros((count, 16), dtype=np.uint8)
+    rc = load().orbg_schedule_export(int(n), int(count), out.ctypes.data_as(ctypes.c_void_p),
+                                     _stream_ptr(stream))
+    _check("orbg_schedule_export", rc)
+    return out

@@ -1,0 +1,81 @@
+// Device-side helpers shared by the ORBGRAND kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ORBG_WAVE 64
+#define ORBG_RANK_SLOTS 256   // LDS slots per wave for permuted columns: rank 0 is the zero column
+#define ORBG_ENTRY_RANKS 16   // ranks held by one 16-byte schedule entry (u8 each, 0 = unused)
+
+namespace orbg {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Orders this wave's LDS traffic: every lane's earlier LDS writes are visible to
+// every lane's later LDS reads (waits for the LDS queue, keeps the compiler
+// from moving accesses across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_xor_reduce(uint64_t v)
+{
+#pragma unroll
+    for (int d = 1; d < ORBG_WAVE; d <<= 1) v ^= __shfl_xor(v, d, ORBG_WAVE);
+    return uniform_u64(v);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Ascending bitonic sort of 64*NK u64 keys held NK per lane.  Element e lives
+// in lane e / NK, register e % NK, so distances below NK are exchanged inside a
+// lane and larger ones across lanes (lane distance d / NK).
+template <int NK>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= ORBG_WAVE * NK; size <<= 1) {
+#pragma unroll
+        for (int d = size >> 1; d > 0; d >>= 1) {
+            if (d < NK) {
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    if ((j & d) == 0) {
+                        const int e = lane * NK + j;
+                        const bool asc = (e & size) == 0;
+                        uint64_t a = key[j], b = key[j | d];
+                        const bool sw = asc ? (a > b) : (a < b);
+                        key[j] = sw ? b : a;
+                        key[j | d] = sw ? a : b;
+                    }
+                }
+            } else {
+                const int ld = d / NK;
+                const bool lower = (lane & ld) == 0;
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    const int e = lane * NK + j;
+                    const bool asc = (e & size) == 0;
+                    uint64_t p = __shfl_xor(key[j], ld, ORBG_WAVE);
+                    const bool take_min = (lower == asc);
+                    const uint64_t mn = key[j] < p ? key[j] : p;
+                    const uint64_t mx = key[j] < p ? p : key[j];
+                    key[j] = take_min ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace orbg

@@ -1,0 +1,27 @@
+// Kernel launchers of liborbgrand (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orbg {
+
+struct DecodeArgs {
+    const float* llr;          // device, nblocks x n
+    int64_t nblocks;
+    int n;
+    const uint64_t* cols;      // device, n packed parity-check columns
+    const uint4* sched;        // device schedule entries
+    const uint8_t* bw;         // device per-batch widths
+    uint64_t slen;             // schedule entries
+    int rdepth;                // ranks whose columns are staged (<= 255)
+    uint64_t budget;
+    const uint8_t* order;      // device, nblocks x 64, or nullptr for plain order
+    uint8_t* cw;               // device, nblocks x n
+    uint64_t* queries;         // device, nblocks
+    uint8_t* abandoned;        // device, nblocks
+    int64_t max_workgroups;    // 0 = one workgroup per 4 blocks
+};
+
+hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream);
+
+}  // namespace orbg

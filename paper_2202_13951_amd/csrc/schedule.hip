@@ -1,0 +1,209 @@
+// Query schedule of basic ORBGRAND, built on the device.
+//
+// The order in which putative noise patterns are tested does not depend on
+// the received block: only the reliability permutation does.  Patterns are
+// sets of reliability ranks 1 <= v_1 < ... < v_w <= n, taken by increasing
+// logistic weight W = sum v_i (Sec. III-B, eqs. (lw), (znwl)), inside one W by
+// increasing Hamming weight w (the union order of eq. (fractionation)), and
+// inside one (W, w) in the order of the Landslide generator (Sec. III-C,
+// Algorithm 2), which is the lexicographic order of v.  The schedule holds the
+// first `len` patterns once per (n, len), as 16-byte entries of u8 ranks, and
+// every block of every decode call reads it.
+//
+// Built by three kernels:
+//   1. class_count_kernel: w-subsets of {1..n} with sum W (a subset-sum count),
+//      then the start offset of every non-empty class (W, w) in the order;
+//   2. class_fill_kernel: one thread per class, walks the class in
+//      lexicographic order by a successor rule and writes its entries;
+//   3. batch_width_kernel: the largest Hamming weight inside each batch of 64
+//      consecutive entries (the trip count of the decode kernel's XOR loop).
+#include "orbg_device.h"
+#include "orbg_internal.h"
+
+namespace orbg {
+
+// counts layout: [ORBG_WMAX_H + 1][ORBG_WCAP + 1]
+__global__ void __launch_bounds__(ORBG_WCAP + 1)
+class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int* wlast_out)
+{
+    __shared__ uint64_t N[ORBG_WMAX_H + 1][ORBG_WCAP + 1];
+    const int W = threadIdx.x;
+#pragma unroll
+    for (int w = 0; w <= ORBG_WMAX_H; ++w) N[w][W] = (w == 0 && W == 0) ? 1ull : 0ull;
+    __syncthreads();
+    const int vmax = n < ORBG_WCAP ? n : ORBG_WCAP;
+    for (int v = 1; v <= vmax; ++v) {
+        const int wtop = v < ORBG_WMAX_H ? v : ORBG_WMAX_H;
+        for (int w = wtop; w >= 1; --w) {
+            const uint64_t add = (W >= v) ? N[w - 1][W - v] : 0ull;
+            N[w][W] += add;
+            __syncthreads();
+        }
+    }
+    if (W != 0) return;
+    // lay the classes out: W ascending, w ascending, until len entries exist
+    uint64_t off = 0;
+    int nc = 0, wlast = 0;
+    for (int Wl = 0; Wl <= ORBG_WLEVEL_MAX && off < len; ++Wl) {
+        for (int w = 0; w <= ORBG_WMAX_H && off < len; ++w) {
+            const uint64_t c = N[w][Wl];
+            if (c == 0) continue;
+            classes[nc].W = Wl;
+            classes[nc].w = w;
+            classes[nc].offset = off;
+            classes[nc].count = c;
+            ++nc;
+            off += c;
+            wlast = Wl;
+        }
+    }
+    // off < len here means the schedule would need W > WCAP or w > WMAX_H
+    *nclass_out = (off >= len) ? nc : -nc - 1;
+    *wlast_out = wlast;
+}
+
+// Largest sum of `cnt` distinct values in [1, n]: n + (n-1) + ... (cnt terms).
+__device__ __forceinline__ int max_sum(int cnt, int n) { return cnt * n - cnt * (cnt - 1) / 2; }
+// Smallest sum of `cnt` distinct values all greater than x.
+__device__ __forceinline__ int min_sum_above(int cnt, int x) { return cnt * x + cnt * (cnt + 1) / 2; }
+
+// Lexicographically smallest strictly increasing fill of v[p..w-1], values in
+// [lo, n], summing to rem.  Caller guarantees feasibility.
+__device__ __forceinline__ void smallest_fill(int* v, int p, int w, int lo, int rem, int n)
+{
+    for (int i = p; i < w; ++i) {
+        const int after = w - 1 - i;                 // elements still to place after v[i]
+        int x = rem - max_sum(after, n);             // the rest can absorb at most max_sum
+        if (x < lo) x = lo;
+        v[i] = x;
+        rem -= x;
+        lo = x + 1;
+    }
+}
+
+__device__ __forceinline__ void store_entry(uint4* out, const int* v, int w)
+{
+    uint32_t word[4] = {0u, 0u, 0u, 0u};
+    for (int i = 0; i < w; ++i) word[i >> 2] |= (uint32_t)v[i] << (8 * (i & 3));
+    *out = make_uint4(word[0], word[1], word[2], word[3]);
+}
+
+__global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes, int nclass,
+                                  uint4* entries)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nclass) return;
+    const int W = classes[c].W, w = classes[c].w;
+    uint64_t g = classes[c].offset;
+    const uint64_t end = classes[c].offset + classes[c].count;
+    int v[ORBG_WMAX_H];
+    if (w == 0) {                                     // the empty pattern
+        if (g < len) entries[g] = make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
+    smallest_fill(v, 0, w, 1, W, n);
+    for (; g < end && g < len; ++g) {
+        store_entry(entries + g, v, w);
+        // successor: the right-most position p < w-1 that can grow by one while
+        // the positions after it still admit a strictly increasing fill
+        int prefix = 0;
+        for (int i = 0; i < w; ++i) prefix += v[i];
+        int p = w - 2;
+        for (; p >= 0; --p) {
+            prefix -= v[p + 1];                       // prefix = sum v[0..p]
+            const int x = v[p] + 1;
+            const int rem = W - (prefix - v[p]) - x;  // what positions p+1.. must hold
+            const int after = w - 1 - p;
+            if (x <= n && rem >= min_sum_above(after, x) && rem <= max_sum(after, n)) {
+                v[p] = x;
+                smallest_fill(v, p + 1, w, x + 1, rem, n);
+                break;
+            }
+        }
+        if (p < 0) break;
+    }
+}
+
+__global__ void batch_width_kernel(const uint4* entries, uint64_t len, uint8_t* bw, uint64_t nbatch,
+                                   int* rmax)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbatch) return;
+    int wmax = 0, r = 0;
+    for (uint64_t g = b * 64; g < b * 64 + 64 && g < len; ++g) {
+        const uint4 e = entries[g];
+        const uint32_t word[4] = {e.x, e.y, e.z, e.w};
+        int w = 0;
+        for (int i = 0; i < ORBG_ENTRY_RANKS; ++i) {
+            const int rk = (word[i >> 2] >> (8 * (i & 3))) & 0xff;
+            if (rk) { w = i + 1; r = rk > r ? rk : r; }
+        }
+        wmax = w > wmax ? w : wmax;
+    }
+    bw[b] = (uint8_t)wmax;
+    atomicMax(rmax, r);
+}
+
+// Builds the schedule of the first `len` patterns for length n on `stream`.
+// Blocks until the class layout is known (one small device-to-host copy).
+int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, char* err, size_t errlen)
+{
+    ClassInfo* d_classes = nullptr;
+    int* d_small = nullptr;
+    const int max_classes = (ORBG_WCAP + 1) * (ORBG_WMAX_H + 1);
+    if (hipMalloc(&d_classes, sizeof(ClassInfo) * max_classes) != hipSuccess ||
+        hipMalloc(&d_small, sizeof(int) * 4) != hipSuccess) {
+        snprintf(err, errlen, "schedule: device allocation failed");
+        (void)hipFree(d_classes); (void)hipFree(d_small);
+        return -2;
+    }
+    (void)hipMemsetAsync(d_small, 0, sizeof(int) * 4, stream);
+    class_count_kernel<<<1, ORBG_WCAP + 1, 0, stream>>>(n, len, d_classes, d_small, d_small + 1);
+    int host_small[2] = {0, 0};
+    (void)hipMemcpyAsync(host_small, d_small, sizeof(int) * 2, hipMemcpyDeviceToHost, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        snprintf(err, errlen, "schedule: class count kernel failed: %s", hipGetErrorString(hipGetLastError()));
+        (void)hipFree(d_classes); (void)hipFree(d_small);
+        return -3;
+    }
+    int nclass = host_small[0];
+    if (nclass < 0) {
+        snprintf(err, errlen, "schedule: %llu patterns need a logistic weight above %d",
+                 (unsigned long long)len, ORBG_WLEVEL_MAX);
+        (void)hipFree(d_classes); (void)hipFree(d_small);
+        return -1;
+    }
+    const uint64_t nbatch = (len + 63) / 64;
+    uint4* d_entries = nullptr;
+    uint8_t* d_bw = nullptr;
+    if (hipMalloc(&d_entries, sizeof(uint4) * nbatch * 64) != hipSuccess ||
+        hipMalloc(&d_bw, nbatch) != hipSuccess) {
+        snprintf(err, errlen, "schedule: cannot allocate %llu entries", (unsigned long long)len);
+        (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
+        return -2;
+    }
+    // entries past len (up to the batch boundary) stay zero: the empty pattern
+    (void)hipMemsetAsync(d_entries, 0, sizeof(uint4) * nbatch * 64, stream);
+    class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, len, d_classes, nclass, d_entries);
+    batch_width_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, d_bw, nbatch,
+                                                                            d_small + 2);
+    int rmax = 0;
+    (void)hipMemcpyAsync(&rmax, d_small + 2, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        snprintf(err, errlen, "schedule: fill kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
+        return -3;
+    }
+    (void)hipFree(d_classes);
+    (void)hipFree(d_small);
+    out->n = n;
+    out->len = len;
+    out->entries = d_entries;
+    out->bw = d_bw;
+    out->nbatch = nbatch;
+    out->rmax = rmax;
+    out->wlast = host_small[1];
+    return 0;
+}
+
+}  // namespace orbg

@@ -1,0 +1,44 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the public
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2202_13951_amd import binding
+
+
+def test_library_exports_header_symbols():
+    L = binding.load()
+    syms = binding.header_symbols()
+    assert {"orbg_decode", "orbg_decode_ordered", "orbg_schedule_export", "orbg_last_error"} <= set(syms)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+@pytest.mark.parametrize("n,k,budget,Hval,msg", [
+    (0, 0, 10, 0, "n = 0"),
+    (1025, 1000, 10, 0, "n = 1025"),
+    (100, 30, 10, 0, "n - k = 70"),
+    (32, 32, 10, 0, "n - k = 0"),
+    (32, 26, 0, 0, "budget = 0"),
+    (32, 26, (1 << 28) + 1, 0, "budget"),
+    (32, 26, 10, 2, "is not 0 or 1"),
+])
+def test_argument_errors_are_einval(n, k, budget, Hval, msg):
+    L = binding.load()
+    m = max(n - k, 1)
+    H = np.zeros((m, max(n, 1)), dtype=np.uint8)
+    H[0, 0] = Hval
+    rc = L.orbg_decode(H.ctypes.data_as(ctypes.c_void_p), None, n, k, budget, 4, None, None, None, None)
+    assert rc == -1
+    assert msg in L.orbg_last_error().decode()
+
+
+def test_ordered_needs_n_at_least_12():
+    L = binding.load()
+    H = np.zeros((3, 10), dtype=np.uint8)
+    rc = L.orbg_decode_ordered(H.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(8), 10, 7, 100, 1,
+                               ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
+                               ctypes.c_void_p(8), None)
+    assert rc == -1 and "n >= 12" in L.orbg_last_error().decode()
