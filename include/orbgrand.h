@@ -22,7 +22,10 @@
  *     queries made, the empty pattern counting as the first), abandoned (one
  *     byte per block: 1 if the budget ran out, then queries == budget and the
  *     codeword row is the hard decision).
- *   - budget: the largest number of queries per block, 1 <= budget <= 2^28.
+ *   - budget: the largest number of queries per block, 1 <= budget <= 2^22
+ *     (4,194,304).  The query schedule stops at logistic weight 99, so for
+ *     short codes (n < 22) a budget close to 2^n that would need patterns of
+ *     larger logistic weight is rejected with ORBG_EINVAL.
  *   - stream: a hipStream_t (NULL = the default stream).  Decodes are
  *     asynchronous on that stream.  The first call for a new H, or for a new
  *     (n, budget) query schedule, allocates device memory and synchronises the
@@ -70,8 +73,9 @@ int orbg_decode(const uint8_t* H, const float* llr, int n, int k, uint64_t budge
  * of 0..63 and gives the order in which block j tests batches 0..63 (ascending
  * index inside a batch).  The plain order then continues from index 4096.
  * `queries` counts positions in this sequence; budget and abandonment are as
- * in orbg_decode.  Requires n >= 12.  Rows that are not permutations give
- * undefined results (the library does not read device memory to check them).
+ * in orbg_decode.  Requires n >= 12.  Bytes are taken modulo 64; a row that
+ * is not a permutation repeats some batches and skips others (the library does
+ * not read device memory to check it).
  * This is the decode step of the learned proposal: ORBGRAND's own order stays
  * the fallback after the reordered prefix.
  */
@@ -84,7 +88,7 @@ int orbg_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint64
  * schedule for length n into the HOST buffer `out` (count x 16 bytes): entry g
  * lists the 1-based reliability ranks flipped by query g + 1 in increasing
  * order, padded with zeros (Sec. III-B/C order as described for orbg_decode).
- * 1 <= count <= 2^28 and count <= 2^n.  Synchronises `stream`.
+ * 1 <= count <= 2^22 and count <= 2^n.  Synchronises `stream`.
  */
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream);
 

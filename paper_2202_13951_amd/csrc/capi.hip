@@ -42,6 +42,10 @@ std::mutex g_mu;
 std::map<std::pair<int, uint64_t>, std::vector<CodeEntry*>> g_codes;
 // (device, n, len) -> schedule
 std::map<std::tuple<int, int, uint64_t>, orbg::Schedule*> g_sched;
+// (device, stream) -> work counter of the persistent decode grid
+std::map<std::pair<int, hipStream_t>, unsigned long long*> g_work;
+// device -> compute units
+std::map<int, int> g_cus;
 
 uint64_t fnv1a(const uint8_t* p, size_t len, uint64_t h = 1469598103934665603ull)
 {
@@ -125,6 +129,30 @@ int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule*
     return ORBG_OK;
 }
 
+// Per-stream work counter (calls on one stream are ordered, so they can share it).
+int get_work_counter(hipStream_t st, unsigned long long** out, int* cus)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_work.find({dev, st});
+    if (it == g_work.end()) {
+        unsigned long long* p = nullptr;
+        if (hipMalloc(&p, 8 * ORBG_XCDS * ORBG_COUNTER_STRIDE) != hipSuccess)
+            return fail(ORBG_ENOMEM, "cannot allocate work counters");
+        it = g_work.emplace(std::make_pair(dev, st), p).first;
+    }
+    *out = it->second;
+    auto c = g_cus.find(dev);
+    if (c == g_cus.end()) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+        c = g_cus.emplace(dev, v).first;
+    }
+    *cus = c->second;
+    return ORBG_OK;
+}
+
 int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
                   void* stream)
@@ -132,7 +160,7 @@ int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     int rc = check_code_args(H, n, k);
     if (rc) return rc;
     if (budget < 1 || budget > ORBG_BUDGET_MAX)
-        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^28]", (unsigned long long)budget);
+        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^22]", (unsigned long long)budget);
     if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
     if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
         return fail(ORBG_EINVAL, "a device buffer is NULL");
@@ -146,13 +174,16 @@ int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     const orbg::Schedule* s = nullptr;
     if ((rc = get_schedule(n, need, st, &s))) return rc;
     if (batch == 0) return ORBG_OK;
+    unsigned long long* work = nullptr;
+    int cus = 0;
+    if ((rc = get_work_counter(st, &work, &cus))) return rc;
     orbg::DecodeArgs a;
     a.llr = llr;
     a.nblocks = batch;
     a.n = n;
     a.cols = cols;
     a.sched = s->entries;
-    a.bw = s->bw;
+    a.bh = s->bh;
     a.slen = s->len;
     a.rdepth = s->rmax < n ? s->rmax : n;
     a.budget = budget;
@@ -160,7 +191,9 @@ int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     a.cw = codeword;
     a.queries = queries;
     a.abandoned = abandoned;
-    a.max_workgroups = 0;
+    a.max_workgroups = (int64_t)cus * 8;
+    a.work = work;
+    a.chunk = 0;
     const hipError_t e = orbg::launch_decode(a, st);
     if (e != hipSuccess) return fail(ORBG_EHIP, "decode launch failed: %s", hipGetErrorString(e));
     return ORBG_OK;
@@ -197,9 +230,13 @@ int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)
     const orbg::Schedule* s = nullptr;
     int rc = get_schedule(n, count, st, &s);
     if (rc) return rc;
-    if (hipMemcpyAsync(out, s->entries, 16 * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return fail(ORBG_EHIP, "schedule copy failed");
+    uint8_t* d_out = nullptr;
+    if (hipMalloc(&d_out, 16 * count) != hipSuccess) return fail(ORBG_ENOMEM, "cannot allocate export buffer");
+    const bool ok = orbg::orbg_unpack_schedule(s, count, d_out, st) == 0 &&
+                    hipMemcpyAsync(out, d_out, 16 * count, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                    hipStreamSynchronize(st) == hipSuccess;
+    (void)hipFree(d_out);
+    if (!ok) return fail(ORBG_EHIP, "schedule export failed");
     return ORBG_OK;
 }
 

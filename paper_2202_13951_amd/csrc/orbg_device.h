@@ -28,11 +28,26 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// XOR of one 32-bit value over the 16 lanes of each DPP row (every lane of the
+// row receives it): quad swaps, half-row mirror, row mirror.  All lanes active.
+__device__ __forceinline__ uint32_t row_xor16(uint32_t v)
+{
+    v ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v ^= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return v;
+}
+
+// XOR of a u64 over the whole wave, returned wave-uniform.  All lanes active.
 __device__ __forceinline__ uint64_t wave_xor_reduce(uint64_t v)
 {
-#pragma unroll
-    for (int d = 1; d < ORBG_WAVE; d <<= 1) v ^= __shfl_xor(v, d, ORBG_WAVE);
-    return uniform_u64(v);
+    const uint32_t lo = row_xor16((uint32_t)v), hi = row_xor16((uint32_t)(v >> 32));
+    const uint32_t l = __builtin_amdgcn_readlane(lo, 0) ^ __builtin_amdgcn_readlane(lo, 16) ^
+                       __builtin_amdgcn_readlane(lo, 32) ^ __builtin_amdgcn_readlane(lo, 48);
+    const uint32_t h = __builtin_amdgcn_readlane(hi, 0) ^ __builtin_amdgcn_readlane(hi, 16) ^
+                       __builtin_amdgcn_readlane(hi, 32) ^ __builtin_amdgcn_readlane(hi, 48);
+    return ((uint64_t)h << 32) | l;
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }

@@ -8,8 +8,13 @@
 #define ORBG_WMAX_H 16       // largest Hamming weight a schedule entry holds
 #define ORBG_WLEVEL_MAX 152  // every pattern of logistic weight <= 152 has at most 16 flips
 #define ORBG_NMAX 1024       // largest code length
+#define ORBG_XCDS 8          // accelerator complex dies per MI355X (workgroups dealt round-robin)
+#define ORBG_COUNTER_STRIDE 32  // u64 stride between work counters (256 B apart)
 #define ORBG_MMAX 64         // largest redundancy n - k (syndromes are one u64)
-#define ORBG_BUDGET_MAX (1ull << 28)
+#define ORBG_BUDGET_MAX (1ull << 22)
+#define ORBG_LOW_RANKS 8     // ranks 1..8 are flipped through a per-block subset table
+#define ORBG_HIGH_SLOTS 7    // ranks above 8 held by one entry (bytes 1..7)
+#define ORBG_WLEVEL_PACKED 99  // every pattern of logistic weight <= 99 has at most 7 ranks above 8
 
 namespace orbg {
 
@@ -24,13 +29,16 @@ struct ClassInfo {
 struct Schedule {
     int n;
     uint64_t len;       // number of valid entries
-    uint4* entries;     // nbatch * 64 entries of 16 u8 ranks (1-based, 0 = none)
-    uint8_t* bw;        // per batch of 64: largest number of ranks in an entry
+    uint2* entries;     // nbatch * 64 packed entries: byte 0 = mask of ranks 1..8 (bit j = rank j+1),
+                        // bytes 1..7 = ranks above 8, ascending, 0 = none
+    uint8_t* bh;        // per batch of 64: largest number of ranks above 8 in an entry
     uint64_t nbatch;
     int rmax;           // largest rank any entry references
     int wlast;          // logistic weight of the last entry
 };
 
 int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, char* err, size_t errlen);
+// Unpacks the first `count` entries to 16-byte lists of 1-based ranks.
+int orbg_unpack_schedule(const Schedule* s, uint64_t count, uint8_t* d_out, hipStream_t stream);
 
 }  // namespace orbg

@@ -10,8 +10,8 @@ struct DecodeArgs {
     int64_t nblocks;
     int n;
     const uint64_t* cols;      // device, n packed parity-check columns
-    const uint4* sched;        // device schedule entries
-    const uint8_t* bw;         // device per-batch widths
+    const uint2* sched;        // device schedule entries (packed, see Schedule)
+    const uint8_t* bh;         // device per-batch count of ranks above 8
     uint64_t slen;             // schedule entries
     int rdepth;                // ranks whose columns are staged (<= 255)
     uint64_t budget;
@@ -19,7 +19,9 @@ struct DecodeArgs {
     uint8_t* cw;               // device, nblocks x n
     uint64_t* queries;         // device, nblocks
     uint8_t* abandoned;        // device, nblocks
-    int64_t max_workgroups;    // 0 = one workgroup per 4 blocks
+    int64_t max_workgroups;    // cap on the persistent grid (0 = no cap)
+    unsigned long long* work;  // device work counter (reset by the launch)
+    int chunk;                 // blocks taken per counter increment
 };
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream);

@@ -7,16 +7,21 @@
 // increasing Hamming weight w (the union order of eq. (fractionation)), and
 // inside one (W, w) in the order of the Landslide generator (Sec. III-C,
 // Algorithm 2), which is the lexicographic order of v.  The schedule holds the
-// first `len` patterns once per (n, len), as 16-byte entries of u8 ranks, and
-// every block of every decode call reads it.
+// first `len` patterns once per (n, len) and every block of every decode call
+// reads it.  An entry is 8 bytes: byte 0 is a mask of the flipped ranks among
+// 1..8 (bit j = rank j + 1; the decoder resolves it through a per-block table of
+// the syndromes of all 256 subsets of the eight least reliable bits), bytes 1..7
+// are the flipped ranks above 8 in increasing order, 0 marking an unused slot.
+// A pattern of logistic weight at most 99 never flips more than seven ranks
+// above 8 (9 + 10 + ... + 16 = 100), which bounds the schedule length.
 //
 // Built by three kernels:
 //   1. class_count_kernel: w-subsets of {1..n} with sum W (a subset-sum count),
 //      then the start offset of every non-empty class (W, w) in the order;
 //   2. class_fill_kernel: one thread per class, walks the class in
 //      lexicographic order by a successor rule and writes its entries;
-//   3. batch_width_kernel: the largest Hamming weight inside each batch of 64
-//      consecutive entries (the trip count of the decode kernel's XOR loop).
+//   3. batch_width_kernel: the largest number of ranks above 8 inside each batch
+//      of 64 consecutive entries (the trip count of the decode kernel's XOR loop).
 #include "orbg_device.h"
 #include "orbg_internal.h"
 
@@ -44,7 +49,7 @@ class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int
     // lay the classes out: W ascending, w ascending, until len entries exist
     uint64_t off = 0;
     int nc = 0, wlast = 0;
-    for (int Wl = 0; Wl <= ORBG_WLEVEL_MAX && off < len; ++Wl) {
+    for (int Wl = 0; Wl <= ORBG_WLEVEL_PACKED && off < len; ++Wl) {
         for (int w = 0; w <= ORBG_WMAX_H && off < len; ++w) {
             const uint64_t c = N[w][Wl];
             if (c == 0) continue;
@@ -81,15 +86,19 @@ __device__ __forceinline__ void smallest_fill(int* v, int p, int w, int lo, int 
     }
 }
 
-__device__ __forceinline__ void store_entry(uint4* out, const int* v, int w)
+__device__ __forceinline__ void store_entry(uint2* out, const int* v, int w)
 {
-    uint32_t word[4] = {0u, 0u, 0u, 0u};
-    for (int i = 0; i < w; ++i) word[i >> 2] |= (uint32_t)v[i] << (8 * (i & 3));
-    *out = make_uint4(word[0], word[1], word[2], word[3]);
+    uint64_t e = 0;
+    int slot = 1;
+    for (int i = 0; i < w; ++i) {
+        if (v[i] <= ORBG_LOW_RANKS) e |= 1ull << (v[i] - 1);
+        else e |= (uint64_t)v[i] << (8 * slot++);
+    }
+    *out = make_uint2((uint32_t)e, (uint32_t)(e >> 32));
 }
 
 __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes, int nclass,
-                                  uint4* entries)
+                                  uint2* entries)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nclass) return;
@@ -98,7 +107,7 @@ __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes,
     const uint64_t end = classes[c].offset + classes[c].count;
     int v[ORBG_WMAX_H];
     if (w == 0) {                                     // the empty pattern
-        if (g < len) entries[g] = make_uint4(0u, 0u, 0u, 0u);
+        if (g < len) entries[g] = make_uint2(0u, 0u);
         return;
     }
     smallest_fill(v, 0, w, 1, W, n);
@@ -124,24 +133,46 @@ __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes,
     }
 }
 
-__global__ void batch_width_kernel(const uint4* entries, uint64_t len, uint8_t* bw, uint64_t nbatch,
+__global__ void batch_width_kernel(const uint2* entries, uint64_t len, uint8_t* bh, uint64_t nbatch,
                                    int* rmax)
 {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbatch) return;
-    int wmax = 0, r = 0;
+    int hmax = 0, r = 0;
     for (uint64_t g = b * 64; g < b * 64 + 64 && g < len; ++g) {
-        const uint4 e = entries[g];
-        const uint32_t word[4] = {e.x, e.y, e.z, e.w};
-        int w = 0;
-        for (int i = 0; i < ORBG_ENTRY_RANKS; ++i) {
-            const int rk = (word[i >> 2] >> (8 * (i & 3))) & 0xff;
-            if (rk) { w = i + 1; r = rk > r ? rk : r; }
+        const uint2 e2 = entries[g];
+        const uint64_t e = ((uint64_t)e2.y << 32) | e2.x;
+        int h = 0;
+        for (int i = 1; i <= ORBG_HIGH_SLOTS; ++i) {
+            const int rk = (int)((e >> (8 * i)) & 0xff);
+            if (rk) { h = i; r = rk > r ? rk : r; }
         }
-        wmax = w > wmax ? w : wmax;
+        const int low = (int)(e & 0xff);
+        if (low) {
+            const int top = 32 - __clz(low);          // highest set bit + 1 = rank
+            r = top > r ? top : r;
+        }
+        hmax = h > hmax ? h : hmax;
     }
-    bw[b] = (uint8_t)wmax;
+    bh[b] = (uint8_t)hmax;
     atomicMax(rmax, r);
+}
+
+__global__ void unpack_kernel(const uint2* entries, uint64_t count, uint8_t* out)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= count) return;
+    const uint2 e2 = entries[g];
+    const uint64_t e = ((uint64_t)e2.y << 32) | e2.x;
+    uint8_t row[16] = {0};
+    int w = 0;
+    for (int j = 0; j < ORBG_LOW_RANKS; ++j)
+        if ((e >> j) & 1) row[w++] = (uint8_t)(j + 1);
+    for (int i = 1; i <= ORBG_HIGH_SLOTS; ++i) {
+        const int rk = (int)((e >> (8 * i)) & 0xff);
+        if (rk) row[w++] = (uint8_t)rk;
+    }
+    for (int i = 0; i < 16; ++i) out[g * 16 + i] = row[i];
 }
 
 // Builds the schedule of the first `len` patterns for length n on `stream`.
@@ -169,21 +200,21 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     int nclass = host_small[0];
     if (nclass < 0) {
         snprintf(err, errlen, "schedule: %llu patterns need a logistic weight above %d",
-                 (unsigned long long)len, ORBG_WLEVEL_MAX);
+                 (unsigned long long)len, ORBG_WLEVEL_PACKED);
         (void)hipFree(d_classes); (void)hipFree(d_small);
         return -1;
     }
     const uint64_t nbatch = (len + 63) / 64;
-    uint4* d_entries = nullptr;
+    uint2* d_entries = nullptr;
     uint8_t* d_bw = nullptr;
-    if (hipMalloc(&d_entries, sizeof(uint4) * nbatch * 64) != hipSuccess ||
+    if (hipMalloc(&d_entries, sizeof(uint2) * nbatch * 64) != hipSuccess ||
         hipMalloc(&d_bw, nbatch) != hipSuccess) {
         snprintf(err, errlen, "schedule: cannot allocate %llu entries", (unsigned long long)len);
         (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
         return -2;
     }
     // entries past len (up to the batch boundary) stay zero: the empty pattern
-    (void)hipMemsetAsync(d_entries, 0, sizeof(uint4) * nbatch * 64, stream);
+    (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * nbatch * 64, stream);
     class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, len, d_classes, nclass, d_entries);
     batch_width_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, d_bw, nbatch,
                                                                             d_small + 2);
@@ -199,11 +230,18 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     out->n = n;
     out->len = len;
     out->entries = d_entries;
-    out->bw = d_bw;
+    out->bh = d_bw;
     out->nbatch = nbatch;
     out->rmax = rmax;
     out->wlast = host_small[1];
     return 0;
+}
+
+int orbg_unpack_schedule(const Schedule* s, uint64_t count, uint8_t* d_out, hipStream_t stream)
+{
+    if (count > s->len) return -1;
+    unpack_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(s->entries, count, d_out);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 }  // namespace orbg
