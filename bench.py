@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-point", action="store_true",
                     help="skip the per-Eb/N0 launches (profiling runs: only the timed launches remain)")
+    ap.add_argument("--ebn0", type=float, nargs="*", default=None,
+                    help="decode only these Eb/N0 points of the workload (diagnosis runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -97,7 +99,11 @@ def main():
     from paper_2202_13951_amd import binding
     from synth import channel, codes
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.ebn0:
+        wl["ebn0"] = [e for e in wl["ebn0"] if any(abs(e - x) < 1e-9 for x in args.ebn0)]
+        assert wl["ebn0"], "no such Eb/N0 point in the workload"
+        wl["desc"] += f" (only Eb/N0 {wl['ebn0']})"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     binding.load()

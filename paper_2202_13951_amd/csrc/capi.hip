@@ -181,6 +181,7 @@ int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     a.llr = llr;
     a.nblocks = batch;
     a.n = n;
+    a.m = n - k;
     a.cols = cols;
     a.sched = s->entries;
     a.bh = s->bh;
@@ -191,7 +192,7 @@ int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     a.cw = codeword;
     a.queries = queries;
     a.abandoned = abandoned;
-    a.max_workgroups = (int64_t)cus * 8;
+    a.max_workgroups = (int64_t)cus * 32;
     a.work = work;
     a.chunk = 0;
     const hipError_t e = orbg::launch_decode(a, st);

@@ -31,16 +31,15 @@
 
 namespace orbg {
 
+// Per-wave LDS: the syndrome type S is u32 when n - k <= 32, else u64.
+template <typename S>
 struct WaveLds {
-    uint64_t T[256];                    // s0 ^ syndromes of subsets of ranks 1..8
-    uint64_t h[ORBG_RANK_SLOTS];        // h[r] = column of rank r (h[0] = 0)
+    S T[256];                           // s0 ^ syndromes of the subsets of ranks 1..8
+    S h[ORBG_RANK_SLOTS];               // h[r] = column of rank r (h[0] = 0)
     uint16_t pi[ORBG_RANK_SLOTS];       // pi[r] = received index of rank r
 };
 
-__device__ __forceinline__ uint32_t entry_byte(const uint2 e, int u)
-{
-    return (u < 4) ? ((e.x >> (8 * u)) & 0xffu) : ((e.y >> (8 * (u - 4))) & 0xffu);
-}
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <int NK>
 __device__ __forceinline__ void load_row(const float* __restrict__ llr_row, int n, float (&x)[NK])
@@ -52,31 +51,55 @@ __device__ __forceinline__ void load_row(const float* __restrict__ llr_row, int 
     }
 }
 
-template <int NK>
+// Mask of the lowest `cnt` lanes.
+__device__ __forceinline__ uint64_t low_lanes(uint32_t cnt) { return cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull); }
+
+// Batch tested at step t: the block's order for the first 64 steps (values
+// taken modulo 64), the plain order afterwards.
+template <bool ORDERED>
+__device__ __forceinline__ uint32_t batch_at(const uint8_t* __restrict__ order_row, uint32_t t)
+{
+    if (!ORDERED || t >= 64) return t;
+    return uniform_u32(order_row[t]) & 63u;
+}
+
+template <typename S>
+__device__ __forceinline__ S wave_xor_reduce_s(S v);
+template <>
+__device__ __forceinline__ uint32_t wave_xor_reduce_s<uint32_t>(uint32_t v)
+{
+    const uint32_t r = row_xor16(v);
+    return __builtin_amdgcn_readlane(r, 0) ^ __builtin_amdgcn_readlane(r, 16) ^
+           __builtin_amdgcn_readlane(r, 32) ^ __builtin_amdgcn_readlane(r, 48);
+}
+template <>
+__device__ __forceinline__ uint64_t wave_xor_reduce_s<uint64_t>(uint64_t v) { return wave_xor_reduce(v); }
+
+template <int NK, bool ORDERED, typename S>
 __device__ __forceinline__ void decode_block(
-    const float (&x)[NK], int n, const uint64_t* __restrict__ s_cols, WaveLds& L,
-    const uint2* __restrict__ sched, const uint8_t* __restrict__ bh, uint64_t slen, int rdepth,
-    uint64_t budget, const uint8_t* __restrict__ order_row,
+    const float (&x)[NK], int n, const S* __restrict__ s_cols, WaveLds<S>& L,
+    const uint2* __restrict__ sched, const uint32_t* __restrict__ bh, uint32_t slen, int rdepth,
+    uint32_t budget, const uint8_t* __restrict__ order_row,
     uint8_t* __restrict__ cw_row, uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
 {
     const int lane = lane_id();
 
     // 1-2. hard decision, base syndrome (the row was staged by the caller)
-    uint64_t acc = 0;
+    S acc = 0;
     bool ybit[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
         const int i = j * ORBG_WAVE + lane;
         ybit[j] = (i < n) && (x[j] > 0.0f);
-        acc ^= ybit[j] ? s_cols[i] : 0ull;
+        acc ^= ybit[j] ? s_cols[i] : (S)0;
     }
-    const uint64_t s0 = wave_xor_reduce(acc);
+    const S s0 = wave_xor_reduce_s<S>(acc);
 
     bool found = false;
-    uint64_t q = budget;
-    uint2 win = make_uint2(0u, 0u);
+    uint32_t q = budget;
+    uint32_t win_lo = 0, win_hi = 0;     // winning entry (wave-uniform)
 
-    if (s0 == 0 && order_row == nullptr) {
+    if (!ORDERED && s0 == 0) {
         found = true;
         q = 1;
     } else {
@@ -90,7 +113,7 @@ __device__ __forceinline__ void decode_block(
         }
         bitonic_sort<NK>(key);
         wave_lds_sync();
-        if (lane == 0) { L.h[0] = 0ull; L.pi[0] = 0; }
+        if (lane == 0) { L.h[0] = 0; L.pi[0] = 0; }
 #pragma unroll
         for (int j = 0; j < NK; ++j) {
             const int e = lane * NK + j;          // rank e + 1
@@ -99,77 +122,92 @@ __device__ __forceinline__ void decode_block(
                 L.h[e + 1] = s_cols[idx];
                 L.pi[e + 1] = (uint16_t)idx;
             } else if (e < ORBG_LOW_RANKS) {
-                L.h[e + 1] = 0ull;                // ranks beyond n (tiny codes)
+                L.h[e + 1] = 0;                   // ranks beyond n (tiny codes)
             }
         }
         wave_lds_sync();
-        uint64_t a = s0;
+        S a = s0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? L.h[b + 1] : 0ull;
-        const uint64_t h7 = L.h[7], h8 = L.h[8];
+        for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? L.h[b + 1] : (S)0;
+        const S h7 = L.h[7], h8 = L.h[8];
         L.T[lane] = a;
         L.T[lane + 64] = a ^ h7;
         L.T[lane + 128] = a ^ h8;
         L.T[lane + 192] = a ^ h7 ^ h8;
         wave_lds_sync();
 
-        // 4. search (step t tests batch bt = order[t] or t; lane l takes entry 64 bt + l,
-        // which is query number 64 t + l + 1)
-        uint64_t t = 0;
-        uint64_t bt = (order_row != nullptr) ? (order_row[0] & 63u) : 0;
-        uint64_t g = bt * ORBG_WAVE + lane;
-        bool valid = ((uint64_t)lane < budget) && (g < slen);
-        uint2 ent = valid ? sched[g] : make_uint2(0u, 0u);
-        int nh = bh[bt];
+        // 4. search.  Step t tests batch bt; lane l takes schedule entry 64 bt + l,
+        // which is query number 64 t + l + 1.  Lanes past the budget or the
+        // schedule read a valid entry and are masked out of the ballot.
+        // Indices fit 32 bits (budget, schedule length <= 2^22).
+        uint32_t t = 0;
+        uint32_t bt = batch_at<ORDERED>(order_row, 0);
+        uint64_t vmask = low_lanes(min(budget, slen - bt * ORBG_WAVE));
+        uint2 ent = sched[min(bt * ORBG_WAVE + lane, slen - 1)];
+        uint32_t nh = bh[bt];
         for (;;) {
-            const uint64_t t1 = t + 1;
-            const uint64_t b1 = (order_row != nullptr && t1 < 64) ? (order_row[t1] & 63u) : t1;
+            const uint32_t t1 = t + 1;
+            const uint32_t b1 = batch_at<ORDERED>(order_row, t1);
             const bool has_next = (t1 * ORBG_WAVE < budget) && (b1 * ORBG_WAVE < slen);
             uint2 ent1 = make_uint2(0u, 0u);
-            int nh1 = 0;
-            bool valid1 = false;
+            uint32_t nh1 = 0;
+            uint64_t vmask1 = 0;
             if (has_next) {
-                const uint64_t g1 = b1 * ORBG_WAVE + lane;
-                valid1 = (t1 * ORBG_WAVE + lane < budget) && (g1 < slen);
-                if (valid1) ent1 = sched[g1];
+                ent1 = sched[min(b1 * ORBG_WAVE + lane, slen - 1)];
                 nh1 = bh[b1];
+                vmask1 = low_lanes(min(budget - t1 * ORBG_WAVE, slen - b1 * ORBG_WAVE));
             }
-            uint64_t s = L.T[ent.x & 0xffu];
-#pragma unroll
-            for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u)
-                if (u <= nh) s ^= L.h[entry_byte(ent, u)];
-            const uint64_t hits = ballot(valid && s == 0);
+            // all lookups issued before the first XOR
+            const S v0 = L.T[ent.x & 0xffu];
+            S v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0;
+            if (nh >= 1) v1 = L.h[(ent.x >> 8) & 0xffu];
+            if (nh >= 2) v2 = L.h[(ent.x >> 16) & 0xffu];
+            if (nh >= 3) v3 = L.h[ent.x >> 24];
+            if (nh >= 4) v4 = L.h[ent.y & 0xffu];
+            if (nh >= 5) v5 = L.h[(ent.y >> 8) & 0xffu];
+            if (nh >= 6) v6 = L.h[(ent.y >> 16) & 0xffu];
+            if (nh >= 7) v7 = L.h[ent.y >> 24];
+            const S syn = v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7;
+            const uint64_t hits = ballot(syn == 0) & vmask;
             if (hits) {
                 const int wl = __builtin_ctzll(hits);
                 found = true;
                 q = t * ORBG_WAVE + wl + 1;
-                win.x = __shfl(ent.x, wl, ORBG_WAVE);
-                win.y = __shfl(ent.y, wl, ORBG_WAVE);
+                win_lo = __builtin_amdgcn_readlane(ent.x, wl);
+                win_hi = __builtin_amdgcn_readlane(ent.y, wl);
                 break;
             }
             if (!has_next) break;
-            t = t1; ent = ent1; nh = nh1; valid = valid1;
+            t = t1; ent = ent1; nh = nh1; vmask = vmask1;
         }
     }
 
-    // 5. output: flip the winning pattern's positions
-    int flip_pos[ORBG_LOW_RANKS + ORBG_HIGH_SLOTS];
+    // 5. output: the hard decision with the winning pattern's positions flipped
+    if ((win_lo | win_hi) == 0) {
 #pragma unroll
-    for (int u = 0; u < ORBG_LOW_RANKS; ++u)
-        flip_pos[u] = (found && ((win.x >> u) & 1u)) ? (int)L.pi[u + 1] : -1;
+        for (int j = 0; j < NK; ++j) {
+            const int i = j * ORBG_WAVE + lane;
+            if (i < n) cw_row[i] = ybit[j] ? 1 : 0;
+        }
+    } else {
+        int flip_pos[ORBG_LOW_RANKS + ORBG_HIGH_SLOTS];
 #pragma unroll
-    for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
-        const uint32_t r = entry_byte(win, u);
-        flip_pos[ORBG_LOW_RANKS + u - 1] = (found && r != 0) ? (int)L.pi[r] : -1;
-    }
+        for (int u = 0; u < ORBG_LOW_RANKS; ++u)
+            flip_pos[u] = ((win_lo >> u) & 1u) ? (int)L.pi[u + 1] : -1;
 #pragma unroll
-    for (int j = 0; j < NK; ++j) {
-        const int i = j * ORBG_WAVE + lane;
-        if (i < n) {
-            bool b = ybit[j];
+        for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
+            const uint32_t r = (u < 4) ? ((win_lo >> (8 * u)) & 0xffu) : ((win_hi >> (8 * (u - 4))) & 0xffu);
+            flip_pos[ORBG_LOW_RANKS + u - 1] = r ? (int)L.pi[r] : -1;
+        }
 #pragma unroll
-            for (int u = 0; u < ORBG_LOW_RANKS + ORBG_HIGH_SLOTS; ++u) b ^= (flip_pos[u] == i);
-            cw_row[i] = b ? 1 : 0;
+        for (int j = 0; j < NK; ++j) {
+            const int i = j * ORBG_WAVE + lane;
+            if (i < n) {
+                bool b = ybit[j];
+#pragma unroll
+                for (int u = 0; u < ORBG_LOW_RANKS + ORBG_HIGH_SLOTS; ++u) b ^= (flip_pos[u] == i);
+                cw_row[i] = b ? 1 : 0;
+            }
         }
     }
     if (lane == 0) {
@@ -179,21 +217,20 @@ __device__ __forceinline__ void decode_block(
     wave_lds_sync();
 }
 
-template <int NK, int WAVES>
-__global__ void __launch_bounds__(WAVES * ORBG_WAVE)
+// One wave per workgroup, so the wave's LDS tables sit at fixed addresses.
+template <int NK, bool ORDERED, typename S>
+__global__ void __launch_bounds__(ORBG_WAVE)
 decode_kernel(const float* __restrict__ llr, int64_t nblocks, int n,
               const uint64_t* __restrict__ cols,
-              const uint2* __restrict__ sched, const uint8_t* __restrict__ bh, uint64_t slen, int rdepth,
-              uint64_t budget, const uint8_t* __restrict__ order,
+              const uint2* __restrict__ sched, const uint32_t* __restrict__ bh, uint32_t slen, int rdepth,
+              uint32_t budget, const uint8_t* __restrict__ order,
               uint8_t* __restrict__ cw, uint64_t* __restrict__ queries, uint8_t* __restrict__ abandoned,
               unsigned long long* __restrict__ work, int chunk)
 {
-    __shared__ uint64_t s_cols[ORBG_WAVE * NK];
-    __shared__ WaveLds s_wave[WAVES];
-    for (int i = threadIdx.x; i < n; i += WAVES * ORBG_WAVE) s_cols[i] = cols[i];
-    __syncthreads();
-    const int wave = threadIdx.x / ORBG_WAVE;
-    WaveLds& L = s_wave[wave];
+    __shared__ S s_cols[ORBG_WAVE * NK];
+    __shared__ WaveLds<S> L;
+    for (int i = threadIdx.x; i < n; i += ORBG_WAVE) s_cols[i] = (S)cols[i];
+    wave_lds_sync();
     const int lane = lane_id();
 
     // XCD-aware work split: workgroups are dealt round-robin to the 8 XCDs, so
@@ -216,8 +253,9 @@ decode_kernel(const float* __restrict__ llr, int64_t nblocks, int n,
             for (int64_t b = b0; b < end; ++b) {
                 float xn[NK];
                 if (b + 1 < end) load_row<NK>(llr + (b + 1) * n, n, xn);   // next row in flight
-                decode_block<NK>(x, n, s_cols, L, sched, bh, slen, rdepth, budget,
-                                 order ? order + b * 64 : nullptr, cw + b * n, queries + b, abandoned + b);
+                decode_block<NK, ORDERED, S>(x, n, s_cols, L, sched, bh, slen, rdepth, budget,
+                                             ORDERED ? order + b * 64 : nullptr, cw + b * n, queries + b,
+                                             abandoned + b);
 #pragma unroll
                 for (int j = 0; j < NK; ++j) x[j] = xn[j];
             }
@@ -231,23 +269,35 @@ __global__ void reset_counter_kernel(unsigned long long* c)
     if (threadIdx.x < ORBG_XCDS) c[threadIdx.x * ORBG_COUNTER_STRIDE] = 0ull;
 }
 
+template <int NK, bool ORDERED, typename S>
+static void launch_one(const DecodeArgs& a, int64_t wgs, int chunk, hipStream_t stream)
+{
+    decode_kernel<NK, ORDERED, S><<<(unsigned)wgs, ORBG_WAVE, 0, stream>>>(
+        a.llr, a.nblocks, a.n, a.cols, a.sched, a.bh, (uint32_t)a.slen, a.rdepth, (uint32_t)a.budget,
+        a.order, a.cw, a.queries, a.abandoned, a.work, chunk);
+}
+
 template <int NK>
 static hipError_t launch_nk(const DecodeArgs& a, hipStream_t stream)
 {
-    constexpr int WAVES = 4;
-    int64_t wgs = (a.nblocks + WAVES - 1) / WAVES;
+    int64_t wgs = a.nblocks;
     if (a.max_workgroups > 0 && wgs > a.max_workgroups) wgs = a.max_workgroups;
     if (wgs < 1) return hipSuccess;
     // about 16 chunks per wave: few atomics, and a short tail when blocks differ
     int chunk = a.chunk;
     if (chunk <= 0) {
-        const int64_t c = a.nblocks / (wgs * WAVES * 16);
+        const int64_t c = a.nblocks / (wgs * 16);
         chunk = (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
     }
     reset_counter_kernel<<<1, 64, 0, stream>>>(a.work);
-    decode_kernel<NK, WAVES><<<(unsigned)wgs, WAVES * ORBG_WAVE, 0, stream>>>(
-        a.llr, a.nblocks, a.n, a.cols, a.sched, a.bh, a.slen, a.rdepth, a.budget, a.order,
-        a.cw, a.queries, a.abandoned, a.work, chunk);
+    const bool s32 = a.m <= 32;
+    if (a.order) {
+        if (s32) launch_one<NK, true, uint32_t>(a, wgs, chunk, stream);
+        else launch_one<NK, true, uint64_t>(a, wgs, chunk, stream);
+    } else {
+        if (s32) launch_one<NK, false, uint32_t>(a, wgs, chunk, stream);
+        else launch_one<NK, false, uint64_t>(a, wgs, chunk, stream);
+    }
     return hipGetLastError();
 }
 

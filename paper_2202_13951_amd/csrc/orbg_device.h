@@ -54,7 +54,9 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Ascending bitonic sort of 64*NK u64 keys held NK per lane.  Element e lives
 // in lane e / NK, register e % NK, so distances below NK are exchanged inside a
-// lane and larger ones across lanes (lane distance d / NK).
+// lane and larger ones across lanes (lane distance d / NK).  Keys must be
+// distinct except for padding.  A compare-exchange is one 64-bit compare, a
+// lane-mask XOR with the stage's direction and two selects.
 template <int NK>
 __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
 {
@@ -67,26 +69,23 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
 #pragma unroll
                 for (int j = 0; j < NK; ++j) {
                     if ((j & d) == 0) {
-                        const int e = lane * NK + j;
-                        const bool asc = (e & size) == 0;
-                        uint64_t a = key[j], b = key[j | d];
-                        const bool sw = asc ? (a > b) : (a < b);
+                        // ascending iff bit `size` of e = lane * NK + j is clear
+                        const bool desc = ((lane * NK + j) & size) != 0;
+                        const uint64_t a = key[j], b = key[j | d];
+                        const bool sw = (a > b) != desc;
                         key[j] = sw ? b : a;
                         key[j | d] = sw ? a : b;
                     }
                 }
             } else {
                 const int ld = d / NK;
-                const bool lower = (lane & ld) == 0;
+                // the lower lane of a pair keeps the minimum in ascending runs
+                const bool keep_min = ((lane & ld) == 0) == (((lane * NK) & size) == 0);
 #pragma unroll
                 for (int j = 0; j < NK; ++j) {
-                    const int e = lane * NK + j;
-                    const bool asc = (e & size) == 0;
-                    uint64_t p = __shfl_xor(key[j], ld, ORBG_WAVE);
-                    const bool take_min = (lower == asc);
-                    const uint64_t mn = key[j] < p ? key[j] : p;
-                    const uint64_t mx = key[j] < p ? p : key[j];
-                    key[j] = take_min ? mn : mx;
+                    const uint64_t p = __shfl_xor(key[j], ld, ORBG_WAVE);
+                    const bool take_p = (p < key[j]) == keep_min;
+                    key[j] = take_p ? p : key[j];
                 }
             }
         }

@@ -9,9 +9,10 @@ struct DecodeArgs {
     const float* llr;          // device, nblocks x n
     int64_t nblocks;
     int n;
+    int m;                     // n - k
     const uint64_t* cols;      // device, n packed parity-check columns
     const uint2* sched;        // device schedule entries (packed, see Schedule)
-    const uint8_t* bh;         // device per-batch count of ranks above 8
+    const uint32_t* bh;        // device per-batch count of ranks above 8
     uint64_t slen;             // schedule entries
     int rdepth;                // ranks whose columns are staged (<= 255)
     uint64_t budget;

@@ -133,7 +133,7 @@ __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes,
     }
 }
 
-__global__ void batch_width_kernel(const uint2* entries, uint64_t len, uint8_t* bh, uint64_t nbatch,
+__global__ void batch_width_kernel(const uint2* entries, uint64_t len, uint32_t* bh, uint64_t nbatch,
                                    int* rmax)
 {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,7 +154,7 @@ __global__ void batch_width_kernel(const uint2* entries, uint64_t len, uint8_t* 
         }
         hmax = h > hmax ? h : hmax;
     }
-    bh[b] = (uint8_t)hmax;
+    bh[b] = (uint32_t)hmax;
     atomicMax(rmax, r);
 }
 
@@ -206,9 +206,9 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     }
     const uint64_t nbatch = (len + 63) / 64;
     uint2* d_entries = nullptr;
-    uint8_t* d_bw = nullptr;
+    uint32_t* d_bw = nullptr;
     if (hipMalloc(&d_entries, sizeof(uint2) * nbatch * 64) != hipSuccess ||
-        hipMalloc(&d_bw, nbatch) != hipSuccess) {
+        hipMalloc(&d_bw, sizeof(uint32_t) * nbatch) != hipSuccess) {
         snprintf(err, errlen, "schedule: cannot allocate %llu entries", (unsigned long long)len);
         (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
         return -2;
