@@ -55,6 +55,35 @@ def algorithmic_ops(q_sum: int, n_sorted: int, n: int) -> float:
     return 4.0 * q_sum + 2.0 * n * math.ceil(math.log2(n)) * n_sorted
 
 
+def kernel_fingerprint() -> str:
+    """sha256 (first 16 hex digits) over the names and contents of the kernel sources."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_13951_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of
+    this workload, or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"decode_kernel_{WORKLOADS[workload]['code']}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_fingerprint"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("source_fingerprint") != kernel_fingerprint() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(H, llr_host_points, budget, target_s=10.0):
     """Times the oracle (as it stands) on the first blocks of every Eb/N0 point."""
     from oracle import oracle as O
@@ -193,7 +222,8 @@ def main():
         "kernel_ms": float(np.mean(kern_ms)),
         "per_point": per_point,
         "roofline": {"bound": "alu", "achieved": ops / kavg / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS, "traffic": None,
+                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS,
+                     "traffic": (profiled_traffic(args.workload) if not args.ebn0 else None),
                      "kernel": "decode_kernel", "ops_per_launch": ops,
                      "hbm": {"achieved_GBps": hbm_bytes / kavg / 1e9, "peak_GBps": PEAK_HBM / 1e9,
                              "frac": hbm_bytes / kavg / PEAK_HBM, "bytes_per_launch": hbm_bytes}},
