@@ -1,11 +1,16 @@
 """Benchmark: decoded blocks/s and queries/s of basic ORBGRAND on one MI355X.
 
-Workload (default): narrow-sense BCH(127,113), t = 2, BPSK over AWGN at
+Default workload: narrow-sense BCH(127,113), t = 2, BPSK over AWGN at
 Eb/N0 = 4.0, 4.5, ..., 7.0 dB, 10^6 blocks per point, query budget 10^5, plain
 ORBGRAND.  One step decodes all 7 x 10^6 blocks (LLRs already resident in HBM)
-with one launch of the decode kernel.  Prints one JSON line.
+with one decode call (light pass + heavy pass).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bch127|rlc32]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bch127|rlc32|mixed]
+
+--workload mixed: random linear codes (64,52), (128,116), (256,240) mixed 1:2:1
+in one persistent launch per Eb/N0 point (3..6 dB, 4x10^6 blocks, budget
+10^6), against the same blocks decoded by one launch per code without the
+heavy pass.
 """
 from __future__ import annotations
 
@@ -35,6 +40,10 @@ WORKLOADS = {
                         "budget 1e5, plain ORBGRAND"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
+    "mixed": dict(codes=["rlc64_52", "rlc128_116", "rlc256_240"], ratio=[1, 2, 1],
+                  ebn0=[3.0, 3.5, 4.0, 4.5, 5.0, 5.5, 6.0], blocks=4 * 10 ** 6, budget=10 ** 6, tune_point=4.5,
+                  desc="RLC (64,52):(128,116):(256,240) = 1:2:1 in one launch, BPSK/AWGN Eb/N0 3..6 dB "
+                       "step 0.5, 4e6 blocks per point, budget 1e6, plain ORBGRAND"),
 }
 
 
@@ -105,74 +114,91 @@ def cpu_baseline(H, llr_host_points, budget, target_s=10.0):
                       f"({nb} blocks, {dt:.1f} s wall)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="bch127", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-per-point", action="store_true",
-                    help="skip the per-Eb/N0 launches (profiling runs: only the timed launches remain)")
-    ap.add_argument("--ebn0", type=float, nargs="*", default=None,
-                    help="decode only these Eb/N0 points of the workload (diagnosis runs)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(blocks are independent: shard the block range over GPUs)", file=sys.stderr)
-        sys.exit(2)
-
+def single_inputs(wl, dev, points=None):
+    """Resident [P * B, n] FP32 LLRs (and sent codewords) of a one-code workload."""
     import torch
-    from paper_2202_13951_amd import binding
     from synth import channel, codes
-
-    wl = dict(WORKLOADS[args.workload])
-    if args.ebn0:
-        wl["ebn0"] = [e for e in wl["ebn0"] if any(abs(e - x) < 1e-9 for x in args.ebn0)]
-        assert wl["ebn0"], "no such Eb/N0 point in the workload"
-        wl["desc"] += f" (only Eb/N0 {wl['ebn0']})"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    binding.load()
     H, G = codes.code(wl["code"])
-    n, k, budget = wl["n"], wl["k"], wl["budget"]
-    P, B = len(wl["ebn0"]), wl["blocks"]
-
-    # inputs: one resident [P * B, n] FP32 LLR array
-    llr = torch.empty((P * B, n), dtype=torch.float32, device=dev)
-    sent = torch.empty((P * B, n), dtype=torch.uint8, device=dev)
-    for p, e in enumerate(wl["ebn0"]):
-        x, c = channel.awgn_llr_torch(G, B, e, seed=1000 + p, device=dev)
+    pts = wl["ebn0"] if points is None else points
+    B, n = wl["blocks"], wl["n"]
+    llr = torch.empty((len(pts) * B, n), dtype=torch.float32, device=dev)
+    sent = torch.empty((len(pts) * B, n), dtype=torch.uint8, device=dev)
+    for p, e in enumerate(pts):
+        seed = 1000 + point_seed_index(wl, e)
+        x, c = channel.awgn_llr_torch(G, B, e, seed=seed, device=dev)
         llr[p * B:(p + 1) * B] = x
         sent[p * B:(p + 1) * B] = c
         del x, c
-    cw = torch.empty((P * B, n), dtype=torch.uint8, device=dev)
+    return H, llr, sent
+
+
+def point_seed_index(wl, e):
+    """Seed index of an Eb/N0 point: its position in the full grid (0.5 dB steps from 3 dB)."""
+    return int(round((e - 3.0) * 2))
+
+
+def mixed_inputs(wl, e, dev):
+    from synth import codes, mixed
+    HG = [codes.code(nm) for nm in wl["codes"]]
+    llr, sent, bc, ro = mixed.mixed_llr_torch([G for _, G in HG], wl["ratio"], wl["blocks"], e,
+                                              seed=2000 + int(round(e * 10)), device=dev)
+    return HG, llr, sent, bc, ro
+
+
+def make_runner(name: str):
+    """(run(params), blocks): one decode of the workload's tuning input per call."""
+    import torch
+    from paper_2202_13951_amd import binding
+    dev = torch.device("cuda:0")
+    wl = WORKLOADS[name]
+    if "codes" in wl:
+        HG, llr, sent, bc, ro = mixed_inputs(wl, wl["tune_point"], dev)
+        ids = [binding.orbg_code_register(H) for H, _ in HG]
+        N = bc.shape[0]
+        cw = torch.empty_like(sent)
+        q = torch.empty(N, dtype=torch.int64, device=dev)
+        ab = torch.empty(N, dtype=torch.uint8, device=dev)
+        return (lambda p: binding.orbg_decode_mixed(ids, bc, ro, llr, wl["budget"], cw, q, ab, params=p)), N
+    H, llr, sent = single_inputs(wl, dev)
+    out = (torch.empty_like(sent), torch.empty(llr.shape[0], dtype=torch.int64, device=dev),
+           torch.empty(llr.shape[0], dtype=torch.uint8, device=dev))
+    return (lambda p: binding.orbg_decode_ex(H, llr, wl["budget"], params=p, out=out)), llr.shape[0]
+
+
+def tuned_params(name: str, use_tuned: bool):
+    from paper_2202_13951_amd import autotune, binding
+    knobs = autotune.load_tuned(name) if use_tuned else None
+    return (binding.LaunchParams(**knobs) if knobs else None), knobs
+
+
+def run_single(args, wl, dev):
+    import torch
+    from paper_2202_13951_amd import binding
+    H, llr, sent = single_inputs(wl, dev)
+    n, budget = wl["n"], wl["budget"]
+    P, B = len(wl["ebn0"]), wl["blocks"]
+    params, knobs = tuned_params(args.workload, not args.no_tuned)
+    cw = torch.empty_like(sent)
     q = torch.empty((P * B,), dtype=torch.int64, device=dev)
     ab = torch.empty((P * B,), dtype=torch.uint8, device=dev)
     out = (cw, q, ab)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-
     for _ in range(args.warmup):
-        binding.orbg_decode(H, llr, budget, out=out)
+        binding.orbg_decode_ex(H, llr, budget, params=params, out=out)
     torch.cuda.synchronize()
-
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
-        binding.orbg_decode(H, llr, budget, out=out)
+        binding.orbg_decode_ex(H, llr, budget, params=params, out=out)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in ev]
-    ms_per_step = wall * 1e3 / args.steps
     blocks = P * B
 
-    # results of the last step: query counts, BLER per point
     q_np = q.cpu().numpy()
     ab_np = ab.cpu().numpy()
     err = (cw != sent).any(dim=1).cpu().numpy()
@@ -183,16 +209,16 @@ def main():
         sl = slice(p * B, (p + 1) * B)
         ne = int(err[sl].sum())
         lo, hi = wilson(ne, B)
-        per_point[f"{e:.1f}"] = {"bler": ne / B, "errors": ne, "bler_ci95": [lo, hi], "mean_queries": float(q_np[sl].mean()),
+        per_point[f"{e:.1f}"] = {"bler": ne / B, "errors": ne, "bler_ci95": [lo, hi],
+                                 "mean_queries": float(q_np[sl].mean()),
                                  "p99_queries": float(np.percentile(q_np[sl], 99)),
                                  "abandoned": int(ab_np[sl].sum())}
-    # per-point throughput (each point decoded alone, kernel time by events)
     for p, e in enumerate([] if args.no_per_point else wl["ebn0"]):
         sl = slice(p * B, (p + 1) * B)
         sub_out = (cw[sl], q[sl], ab[sl])
         a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a_.record(stream)
-        binding.orbg_decode(H, llr[sl], budget, out=sub_out)
+        binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=sub_out)
         b_.record(stream)
         torch.cuda.synchronize()
         t = a_.elapsed_time(b_) / 1e3
@@ -209,22 +235,23 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "code": wl["code"], "n": n, "k": k, "ebn0_db": wl["ebn0"],
+        "config": {"workload": wl["desc"], "code": wl["code"], "n": n, "k": wl["k"], "ebn0_db": wl["ebn0"],
                    "blocks_per_step": blocks, "budget": budget},
         "queries_per_s": q_sum / (wall / args.steps),
         "mean_queries": q_sum / blocks,
         "kernel_ms": float(np.mean(kern_ms)),
+        "launch_params": knobs if knobs else "library defaults",
         "per_point": per_point,
         "roofline": {"bound": "alu", "achieved": ops / kavg / 1e12, "peak": PEAK_INT32_OPS / 1e12,
                      "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS,
-                     "traffic": (profiled_traffic(args.workload) if not args.ebn0 else None),
-                     "kernel": "decode_kernel", "ops_per_launch": ops,
+                     "traffic": profiled_traffic(args.workload),
+                     "kernel": "light_kernel + heavy_kernel (one decode call)", "ops_per_launch": ops,
                      "hbm": {"achieved_GBps": hbm_bytes / kavg / 1e9, "peak_GBps": PEAK_HBM / 1e9,
                              "frac": hbm_bytes / kavg / PEAK_HBM, "bytes_per_launch": hbm_bytes}},
     }
@@ -238,6 +265,123 @@ def main():
         idx = [np.arange(p * B, p * B + min(B, 50000)) for p in range(P)]
         host_pts = [llr[torch.from_numpy(i).to(dev)].cpu().numpy() for i in idx]
         result["cpu_baseline"] = cpu_baseline(H, host_pts, budget)
+    return result
+
+
+def run_mixed(args, wl, dev):
+    """Per Eb/N0 point: the tuned persistent mixed launch, and one launch per code
+    without the heavy pass, on the same blocks (results compared bit for bit)."""
+    import torch
+    from paper_2202_13951_amd import binding
+    params, knobs = tuned_params(args.workload, not args.no_tuned)
+    naive = binding.LaunchParams(split_steps=0)
+    stream = torch.cuda.current_stream()
+    points, tot_blocks, tot_ms, tot_naive_ms, tot_q = {}, 0, 0.0, 0.0, 0
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    for e in wl["ebn0"]:
+        HG, llr, sent, bc, ro = mixed_inputs(wl, e, dev)
+        ids = [binding.orbg_code_register(H) for H, _ in HG]
+        N = bc.shape[0]
+        cw = torch.empty_like(sent)
+        q = torch.empty(N, dtype=torch.int64, device=dev)
+        ab = torch.empty(N, dtype=torch.uint8, device=dev)
+
+        def mixed_fn():
+            binding.orbg_decode_mixed(ids, bc, ro, llr, wl["budget"], cw, q, ab, params=params)
+        for _ in range(args.warmup):
+            mixed_fn()
+        ms = [timed(mixed_fn) for _ in range(args.steps)]
+        print(f"mixed {e} dB: {np.median(ms):.2f} ms", file=sys.stderr, flush=True)
+        # naive: per-code row-major copies, one launch each, no heavy pass
+        per_code = []
+        for ci, (H, G) in enumerate(HG):
+            n = H.shape[1]
+            idx = torch.nonzero(bc == ci).flatten()
+            rows = llr[(ro[idx][:, None] + torch.arange(n, device=dev)[None, :])].contiguous()
+            per_code.append((H, idx, rows, n))
+        outs = [(torch.empty(r.shape, dtype=torch.uint8, device=dev),
+                 torch.empty(r.shape[0], dtype=torch.int64, device=dev),
+                 torch.empty(r.shape[0], dtype=torch.uint8, device=dev)) for _, _, r, _ in per_code]
+
+        def naive_fn():
+            for (H, idx, rows, n), o in zip(per_code, outs):
+                binding.orbg_decode_ex(H, rows, wl["budget"], params=naive, out=o)
+        naive_fn()
+        nms = [timed(naive_fn) for _ in range(args.steps)]
+        print(f"naive {e} dB: {np.median(nms):.2f} ms", file=sys.stderr, flush=True)
+        same = True
+        errs = torch.zeros(N, dtype=torch.bool, device=dev)
+        for (H, idx, rows, n), o in zip(per_code, outs):
+            pos = ro[idx][:, None] + torch.arange(n, device=dev)[None, :]
+            same &= bool((q[idx] == o[1]).all()) and bool((ab[idx] == o[2]).all())
+            same &= bool((cw[pos] == o[0]).all())
+            errs[idx] = (cw[pos] != sent[pos]).any(dim=1)
+        ne = int(errs.sum())
+        qs = int(q.sum())
+        m, nm = float(np.median(ms)), float(np.median(nms))
+        points[f"{e:.1f}"] = {"blocks_per_s": N / (m / 1e3), "naive_blocks_per_s": N / (nm / 1e3),
+                              "speedup_vs_naive": nm / m, "ms": m, "naive_ms": nm, "mean_queries": qs / N,
+                              "bler": ne / N, "bler_ci95": list(wilson(ne, N)), "abandoned": int(ab.sum()),
+                              "identical_to_naive": same}
+        tot_blocks += N
+        tot_ms += m
+        tot_naive_ms += nm
+        tot_q += qs
+        del HG, llr, sent, bc, ro, cw, q, ab, per_code, outs
+        torch.cuda.empty_cache()
+    return {
+        "metric": METRIC, "value": tot_blocks / (tot_ms / 1e3), "unit": "blocks/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": tot_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "codes": wl["codes"], "ratio": wl["ratio"], "ebn0_db": wl["ebn0"],
+                   "blocks_per_point": wl["blocks"], "budget": wl["budget"]},
+        "queries_per_s": tot_q / (tot_ms / 1e3), "naive_value": tot_blocks / (tot_naive_ms / 1e3),
+        "speedup_vs_naive": tot_naive_ms / tot_ms, "launch_params": knobs if knobs else "library defaults",
+        "per_point": points,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bch127", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-point", action="store_true",
+                    help="skip the per-Eb/N0 launches (profiling runs: only the timed launches remain)")
+    ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
+    ap.add_argument("--ebn0", type=float, nargs="*", default=None,
+                    help="decode only these Eb/N0 points of the workload (diagnosis runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(blocks are independent: shard the block range over GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_13951_amd import binding
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    binding.load()
+    wl = dict(WORKLOADS[args.workload])
+    if args.ebn0:
+        wl["ebn0"] = [e for e in wl["ebn0"] if any(abs(e - x) < 1e-9 for x in args.ebn0)]
+        assert wl["ebn0"], "no such Eb/N0 point in the workload"
+        wl["desc"] += f" (only Eb/N0 {wl['ebn0']})"
+    result = run_mixed(args, wl, dev) if "codes" in wl else run_single(args, wl, dev)
+    if args.ebn0 and "roofline" in result:
+        result["roofline"]["traffic"] = None
     print(json.dumps(result), flush=True)
 
 

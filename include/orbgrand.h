@@ -48,6 +48,25 @@ extern "C" {
 #define ORBG_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
 
 /*
+ * Launch shape of a decode (the knobs the autotuner sets).  Any field left 0
+ * takes the library default (split_steps: -1 takes the default, 0 disables the
+ * heavy pass).  Decodes run in two passes: a light pass of persistent
+ * one-wave workgroups over all blocks, which gives up on a block after
+ * `split_steps` steps of 64 queries, and a heavy pass in which workgroups of
+ * `heavy_waves` waves each share one such block, taking its steps in turn.  The
+ * decoded result does not depend on these values.
+ */
+typedef struct orbg_launch_params {
+    int workgroups_per_cu;        /* light pass, 1..64 (default 32) */
+    int chunk;                    /* blocks taken per work-counter increment, 1..4096 (default: about
+                                     16 increments per wave) */
+    int split_steps;              /* -1 = default (64), 0 = no heavy pass, else steps before the split;
+                                     an ordered decode moves values below 64 up to 64 */
+    int heavy_waves;              /* 4, 8 or 16 (default 8) */
+    int heavy_workgroups_per_cu;  /* heavy pass, 1..16 (default 2) */
+} orbg_launch_params;
+
+/*
  * Plain basic-ORBGRAND decode of `batch` blocks of one linear code.
  *
  * Follows Algorithm 1 (GRAND: test putative noise patterns from most to least
@@ -82,6 +101,44 @@ int orbg_decode(const uint8_t* H, const float* llr, int n, int k, uint64_t budge
 int orbg_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
                         int64_t batch, const uint8_t* order, uint8_t* codeword,
                         uint64_t* queries, uint8_t* abandoned, void* stream);
+
+/*
+ * orbg_decode / orbg_decode_ordered with an explicit launch shape.  `order` may
+ * be NULL (plain order) or as in orbg_decode_ordered; `params` may be NULL
+ * (defaults).  Results are identical for every valid `params`.
+ */
+int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                   int64_t batch, const uint8_t* order, uint8_t* codeword, uint64_t* queries,
+                   uint8_t* abandoned, const orbg_launch_params* params, void* stream);
+
+/*
+ * Registers a parity-check matrix (host, as for orbg_decode) for mixed-code
+ * decodes and returns its id in *code_id.  Registering the same H twice gives
+ * two ids for one cached copy.  Allocates and synchronises the device on first
+ * sight of an H.
+ */
+int orbg_code_register(const uint8_t* H, int n, int k, int* code_id);
+
+/* Forgets a registered id (the packed columns stay cached for later use). */
+int orbg_code_release(int code_id);
+
+/*
+ * Decode `batch` blocks of up to 8 different codes in one launch (basic
+ * ORBGRAND as in orbg_decode, for every block with its own code).
+ * codes: HOST array of `ncodes` registered ids (1 <= ncodes <= 8, every code
+ * with n <= 256, the n of all codes summing to at most 2048).
+ * block_code: DEVICE u8 per block, an index into `codes`.
+ * row_offset: DEVICE i64 per block, the offset (in elements) of the block's row
+ * both in `llr` (FP32) and in `codeword` (bytes); rows hold the block's own n
+ * values.  queries/abandoned: DEVICE, one entry per block.  Offsets and code
+ * indices are not checked on the device: they must lie inside the buffers.
+ * Blocks that need many queries move to the heavy pass and are searched by
+ * several waves; the result is the same as orbg_decode's for each block.
+ */
+int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code,
+                      const int64_t* row_offset, const float* llr, int64_t batch,
+                      uint64_t budget, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                      const orbg_launch_params* params, void* stream);
 
 /*
  * Copies the first `count` entries of the library's basic-ORBGRAND query

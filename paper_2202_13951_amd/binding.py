@@ -20,6 +20,18 @@ ORBG_OK = 0
 _lib = None
 
 
+class LaunchParams(ctypes.Structure):
+    """orbg_launch_params: 0 fields take the library defaults (split_steps: -1)."""
+    _fields_ = [("workgroups_per_cu", ctypes.c_int), ("chunk", ctypes.c_int), ("split_steps", ctypes.c_int),
+                ("heavy_waves", ctypes.c_int), ("heavy_workgroups_per_cu", ctypes.c_int)]
+
+    def __init__(self, workgroups_per_cu=0, chunk=0, split_steps=-1, heavy_waves=0, heavy_workgroups_per_cu=0):
+        super().__init__(workgroups_per_cu, chunk, split_steps, heavy_waves, heavy_workgroups_per_cu)
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class OrbgError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} returned {code}: {msg}")
@@ -39,6 +51,14 @@ def load():
     L.orbg_decode.restype = ci
     L.orbg_decode_ordered.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp, vp]
     L.orbg_decode_ordered.restype = ci
+    L.orbg_decode_ex.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp, vp, vp]
+    L.orbg_decode_ex.restype = ci
+    L.orbg_code_register.argtypes = [vp, ci, ci, ctypes.POINTER(ci)]
+    L.orbg_code_register.restype = ci
+    L.orbg_code_release.argtypes = [ci]
+    L.orbg_code_release.restype = ci
+    L.orbg_decode_mixed.argtypes = [vp, ci, vp, vp, vp, i64, u64, vp, vp, vp, vp, vp]
+    L.orbg_decode_mixed.restype = ci
     L.orbg_schedule_export.argtypes = [ci, u64, vp, vp]
     L.orbg_schedule_export.restype = ci
     L.orbg_last_error.argtypes = []
@@ -109,6 +129,59 @@ def orbg_decode_ordered(H, llr, budget: int, order, out=None, stream=None):
                                     ctypes.c_void_p(ab.data_ptr()), _stream_ptr(stream))
     _check("orbg_decode_ordered", rc)
     return cw, q, ab
+
+
+def _params_ptr(params):
+    return ctypes.byref(params) if params is not None else None
+
+
+def orbg_decode_ex(H, llr, budget: int, order=None, params: LaunchParams | None = None, out=None, stream=None):
+    """orbg_decode (order None) or orbg_decode_ordered with an explicit launch shape."""
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    assert llr.is_cuda and llr.is_contiguous() and llr.dim() == 2 and llr.shape[1] == n
+    N = llr.shape[0]
+    if order is not None:
+        assert order.is_cuda and order.is_contiguous() and tuple(order.shape) == (N, 64)
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    rc = load().orbg_decode_ex(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
+                               int(budget), N, ctypes.c_void_p(order.data_ptr()) if order is not None else None,
+                               ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                               ctypes.c_void_p(ab.data_ptr()), _params_ptr(params), _stream_ptr(stream))
+    _check("orbg_decode_ex", rc)
+    return cw, q, ab
+
+
+def orbg_code_register(H) -> int:
+    """Registers a parity-check matrix for mixed decodes; returns its id."""
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    cid = ctypes.c_int(-1)
+    rc = load().orbg_code_register(Hn.ctypes.data_as(ctypes.c_void_p), n, n - m, ctypes.byref(cid))
+    _check("orbg_code_register", rc)
+    return cid.value
+
+
+def orbg_code_release(code_id: int) -> None:
+    _check("orbg_code_release", load().orbg_code_release(int(code_id)))
+
+
+def orbg_decode_mixed(code_ids, block_code, row_offset, llr, budget: int, codeword, queries, abandoned,
+                      params: LaunchParams | None = None, stream=None):
+    """Mixed-code decode.  code_ids: registered ids; block_code: CUDA uint8 [N] index into
+    code_ids; row_offset: CUDA int64 [N] element offset of each row in llr (float32, 1-D) and
+    codeword (uint8, 1-D); queries: CUDA int64 [N]; abandoned: CUDA uint8 [N]."""
+    ids = (ctypes.c_int * len(code_ids))(*[int(c) for c in code_ids])
+    N = block_code.shape[0]
+    for t in (block_code, row_offset, llr, codeword, queries, abandoned):
+        assert t.is_cuda and t.is_contiguous()
+    assert row_offset.shape[0] == N and queries.shape[0] == N and abandoned.shape[0] == N
+    rc = load().orbg_decode_mixed(ids, len(code_ids), ctypes.c_void_p(block_code.data_ptr()),
+                                  ctypes.c_void_p(row_offset.data_ptr()), ctypes.c_void_p(llr.data_ptr()), N,
+                                  int(budget), ctypes.c_void_p(codeword.data_ptr()),
+                                  ctypes.c_void_p(queries.data_ptr()), ctypes.c_void_p(abandoned.data_ptr()),
+                                  _params_ptr(params), _stream_ptr(stream))
+    _check("orbg_decode_mixed", rc)
 
 
 def orbg_schedule_export(n: int, count: int, stream=None) -> np.ndarray:

@@ -1,5 +1,6 @@
 // C-ABI front end of liborbgrand: argument checks, device caches of packed
-// parity-check columns and query schedules, kernel launches.
+// parity-check columns and query schedules, per-stream work space, kernel
+// launches.
 #include "orbgrand.h"
 
 #include <hip/hip_runtime.h>
@@ -32,18 +33,27 @@ int fail(int code, const char* fmt, ...)
 }
 
 struct CodeEntry {
+    int dev = 0;
     int n = 0, k = 0;
     std::vector<uint8_t> H;     // host copy, for exact cache matching
     uint64_t* d_cols = nullptr;
 };
 
+struct Workspace {
+    unsigned long long* ctrs = nullptr;
+    int64_t* heavy = nullptr;
+    int64_t heavy_cap = 0;
+};
+
 std::mutex g_mu;
 // (device, hash) -> codes with that hash
 std::map<std::pair<int, uint64_t>, std::vector<CodeEntry*>> g_codes;
+// registered code ids -> code
+std::vector<CodeEntry*> g_registry;
 // (device, n, len) -> schedule
 std::map<std::tuple<int, int, uint64_t>, orbg::Schedule*> g_sched;
-// (device, stream) -> work counter of the persistent decode grid
-std::map<std::pair<int, hipStream_t>, unsigned long long*> g_work;
+// (device, stream) -> work space
+std::map<std::pair<int, hipStream_t>, Workspace> g_work;
 // device -> compute units
 std::map<int, int> g_cus;
 
@@ -66,7 +76,7 @@ int check_code_args(const uint8_t* H, int n, int k)
 }
 
 // Packed columns of H on the current device (cached by contents).
-int get_code(const uint8_t* H, int n, int k, const uint64_t** cols)
+int get_code(const uint8_t* H, int n, int k, CodeEntry** out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
@@ -77,12 +87,13 @@ int get_code(const uint8_t* H, int n, int k, const uint64_t** cols)
     std::lock_guard<std::mutex> lk(g_mu);
     auto& bucket = g_codes[{dev, h}];
     for (CodeEntry* c : bucket)
-        if (c->n == n && c->k == k && std::memcmp(c->H.data(), H, sz) == 0) { *cols = c->d_cols; return ORBG_OK; }
+        if (c->n == n && c->k == k && std::memcmp(c->H.data(), H, sz) == 0) { *out = c; return ORBG_OK; }
     std::vector<uint64_t> packed(n, 0ull);
     for (int r = 0; r < n - k; ++r)
         for (int i = 0; i < n; ++i)
             if (H[(size_t)r * n + i]) packed[i] |= 1ull << r;
     CodeEntry* c = new CodeEntry;
+    c->dev = dev;
     c->n = n; c->k = k;
     c->H.assign(H, H + sz);
     if (hipMalloc(&c->d_cols, sizeof(uint64_t) * n) != hipSuccess) {
@@ -95,7 +106,7 @@ int get_code(const uint8_t* H, int n, int k, const uint64_t** cols)
         return fail(ORBG_EHIP, "copy of packed columns failed");
     }
     bucket.push_back(c);
-    *cols = c->d_cols;
+    *out = c;
     return ORBG_OK;
 }
 
@@ -129,20 +140,31 @@ int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule*
     return ORBG_OK;
 }
 
-// Per-stream work counter (calls on one stream are ordered, so they can share it).
-int get_work_counter(hipStream_t st, unsigned long long** out, int* cus)
+// Per-stream counters and heavy-block list (calls on one stream are ordered,
+// so they can share them).  Grows the list to `heavy_need` entries.
+int get_workspace(hipStream_t st, int64_t heavy_need, Workspace** out, int* cus)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_work.find({dev, st});
-    if (it == g_work.end()) {
-        unsigned long long* p = nullptr;
-        if (hipMalloc(&p, 8 * ORBG_XCDS * ORBG_COUNTER_STRIDE) != hipSuccess)
-            return fail(ORBG_ENOMEM, "cannot allocate work counters");
-        it = g_work.emplace(std::make_pair(dev, st), p).first;
+    Workspace& w = g_work[{dev, st}];
+    if (!w.ctrs && hipMalloc(&w.ctrs, sizeof(unsigned long long) * ORBG_CTR_WORDS) != hipSuccess) {
+        w.ctrs = nullptr;
+        return fail(ORBG_ENOMEM, "cannot allocate work counters");
     }
-    *out = it->second;
+    if (heavy_need > w.heavy_cap) {
+        // the old list may still be read by work queued on this stream
+        if (w.heavy && (hipStreamSynchronize(st) != hipSuccess || hipFree(w.heavy) != hipSuccess))
+            return fail(ORBG_EHIP, "cannot release the heavy-block list");
+        w.heavy = nullptr;
+        w.heavy_cap = 0;
+        if (hipMalloc(&w.heavy, sizeof(int64_t) * heavy_need) != hipSuccess) {
+            w.heavy = nullptr;
+            return fail(ORBG_ENOMEM, "cannot allocate a heavy-block list of %lld entries", (long long)heavy_need);
+        }
+        w.heavy_cap = heavy_need;
+    }
+    *out = &w;
     auto c = g_cus.find(dev);
     if (c == g_cus.end()) {
         int v = 0;
@@ -153,48 +175,105 @@ int get_work_counter(hipStream_t st, unsigned long long** out, int* cus)
     return ORBG_OK;
 }
 
-int decode_common(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
-                  const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
-                  void* stream)
+orbg::LaunchParams resolve_params(const orbg_launch_params* p, bool ordered)
 {
-    int rc = check_code_args(H, n, k);
+    orbg::LaunchParams r;
+    r.wg_per_cu = 32;
+    r.chunk = 0;
+    r.split_steps = 64;
+    r.heavy_waves = 8;
+    r.heavy_wg_per_cu = 2;
+    if (p) {
+        if (p->workgroups_per_cu > 0) r.wg_per_cu = p->workgroups_per_cu;
+        if (p->chunk > 0) r.chunk = p->chunk;
+        if (p->split_steps >= 0) r.split_steps = p->split_steps;
+        if (p->heavy_waves > 0) r.heavy_waves = p->heavy_waves;
+        if (p->heavy_workgroups_per_cu > 0) r.heavy_wg_per_cu = p->heavy_workgroups_per_cu;
+    }
+    // the reordered prefix (64 steps) always stays in the light pass
+    if (ordered && r.split_steps > 0 && r.split_steps < 64) r.split_steps = 64;
+    return r;
+}
+
+int check_params(const orbg_launch_params* p)
+{
+    if (!p) return ORBG_OK;
+    if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 64)
+        return fail(ORBG_EINVAL, "workgroups_per_cu = %d outside [0, 64]", p->workgroups_per_cu);
+    if (p->chunk < 0 || p->chunk > 4096) return fail(ORBG_EINVAL, "chunk = %d outside [0, 4096]", p->chunk);
+    if (p->split_steps < -1) return fail(ORBG_EINVAL, "split_steps = %d below -1", p->split_steps);
+    if (p->heavy_waves != 0 && p->heavy_waves != 4 && p->heavy_waves != 8 && p->heavy_waves != 16)
+        return fail(ORBG_EINVAL, "heavy_waves = %d is not 0, 4, 8 or 16", p->heavy_waves);
+    if (p->heavy_workgroups_per_cu < 0 || p->heavy_workgroups_per_cu > 16)
+        return fail(ORBG_EINVAL, "heavy_workgroups_per_cu = %d outside [0, 16]", p->heavy_workgroups_per_cu);
+    return ORBG_OK;
+}
+
+int keys_per_lane(int n)
+{
+    int nk = 1;
+    while (nk * 64 < n) nk <<= 1;
+    return nk;
+}
+
+// Fills one code descriptor (schedule for `need` queries).
+int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_base, orbg::CodeDesc* d)
+{
+    if (c->n < 63 && need > (1ull << c->n)) need = 1ull << c->n;
+    const orbg::Schedule* s = nullptr;
+    int rc = get_schedule(c->n, need, st, &s);
     if (rc) return rc;
+    d->n = c->n;
+    d->m = c->n - c->k;
+    d->nk = keys_per_lane(c->n);
+    d->rdepth = s->rmax < c->n ? s->rmax : c->n;
+    d->slen = (uint32_t)s->len;
+    d->col_base = col_base;
+    d->cols = c->d_cols;
+    d->sched = s->entries;
+    d->bh = s->bh;
+    return ORBG_OK;
+}
+
+int check_budget(uint64_t budget, int64_t batch)
+{
     if (budget < 1 || budget > ORBG_BUDGET_MAX)
         return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^22]", (unsigned long long)budget);
     if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
+    return ORBG_OK;
+}
+
+int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                  const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                  const orbg_launch_params* params, void* stream)
+{
+    int rc = check_code_args(H, n, k);
+    if (rc) return rc;
+    if ((rc = check_budget(budget, batch)) || (rc = check_params(params))) return rc;
     if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
         return fail(ORBG_EINVAL, "a device buffer is NULL");
     if (order && n < 12) return fail(ORBG_EINVAL, "a batch order needs n >= 12 (got %d)", n);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const uint64_t* cols = nullptr;
-    if ((rc = get_code(H, n, k, &cols))) return rc;
-    uint64_t need = budget;
-    if (order && need < 4096) need = 4096;
-    if (n < 63 && need > (1ull << n)) need = 1ull << n;
-    const orbg::Schedule* s = nullptr;
-    if ((rc = get_schedule(n, need, st, &s))) return rc;
-    if (batch == 0) return ORBG_OK;
-    unsigned long long* work = nullptr;
-    int cus = 0;
-    if ((rc = get_work_counter(st, &work, &cus))) return rc;
+    CodeEntry* code = nullptr;
+    if ((rc = get_code(H, n, k, &code))) return rc;
     orbg::DecodeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.codes.ncodes = 1;
+    if ((rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]))) return rc;
+    if (batch == 0) return ORBG_OK;
+    a.p = resolve_params(params, order != nullptr);
+    Workspace* w = nullptr;
+    if ((rc = get_workspace(st, a.p.split_steps > 0 ? batch : 0, &w, &a.cus))) return rc;
+    a.mixed = false;
     a.llr = llr;
     a.nblocks = batch;
-    a.n = n;
-    a.m = n - k;
-    a.cols = cols;
-    a.sched = s->entries;
-    a.bh = s->bh;
-    a.slen = s->len;
-    a.rdepth = s->rmax < n ? s->rmax : n;
-    a.budget = budget;
+    a.budget = (uint32_t)budget;
     a.order = order;
     a.cw = codeword;
     a.queries = queries;
     a.abandoned = abandoned;
-    a.max_workgroups = (int64_t)cus * 32;
-    a.work = work;
-    a.chunk = 0;
+    a.ctrs = w->ctrs;
+    a.heavy = a.p.split_steps > 0 ? w->heavy : nullptr;
     const hipError_t e = orbg::launch_decode(a, st);
     if (e != hipSuccess) return fail(ORBG_EHIP, "decode launch failed: %s", hipGetErrorString(e));
     return ORBG_OK;
@@ -208,7 +287,7 @@ int orbg_decode(const uint8_t* H, const float* llr, int n, int k, uint64_t budge
                 uint8_t* codeword, uint64_t* queries, uint8_t* abandoned, void* stream)
 {
     g_err.clear();
-    return decode_common(H, llr, n, k, budget, batch, nullptr, codeword, queries, abandoned, stream);
+    return decode_single(H, llr, n, k, budget, batch, nullptr, codeword, queries, abandoned, nullptr, stream);
 }
 
 int orbg_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
@@ -217,7 +296,98 @@ int orbg_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint64
 {
     g_err.clear();
     if (!order && batch > 0) return fail(ORBG_EINVAL, "order is NULL");
-    return decode_common(H, llr, n, k, budget, batch, order, codeword, queries, abandoned, stream);
+    return decode_single(H, llr, n, k, budget, batch, order, codeword, queries, abandoned, nullptr, stream);
+}
+
+int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                   const orbg_launch_params* params, void* stream)
+{
+    g_err.clear();
+    return decode_single(H, llr, n, k, budget, batch, order, codeword, queries, abandoned, params, stream);
+}
+
+int orbg_code_register(const uint8_t* H, int n, int k, int* code_id)
+{
+    g_err.clear();
+    int rc = check_code_args(H, n, k);
+    if (rc) return rc;
+    if (!code_id) return fail(ORBG_EINVAL, "code_id is NULL");
+    CodeEntry* c = nullptr;
+    if ((rc = get_code(H, n, k, &c))) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (size_t i = 0; i < g_registry.size(); ++i)
+        if (!g_registry[i]) { g_registry[i] = c; *code_id = (int)i; return ORBG_OK; }
+    g_registry.push_back(c);
+    *code_id = (int)g_registry.size() - 1;
+    return ORBG_OK;
+}
+
+int orbg_code_release(int code_id)
+{
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (code_id < 0 || code_id >= (int)g_registry.size() || !g_registry[code_id])
+        return fail(ORBG_EINVAL, "code id %d is not registered", code_id);
+    g_registry[code_id] = nullptr;     // the packed columns stay cached by content
+    return ORBG_OK;
+}
+
+int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const int64_t* row_offset,
+                      const float* llr, int64_t batch, uint64_t budget, uint8_t* codeword, uint64_t* queries,
+                      uint8_t* abandoned, const orbg_launch_params* params, void* stream)
+{
+    g_err.clear();
+    int rc = check_budget(budget, batch);
+    if (rc || (rc = check_params(params))) return rc;
+    if (!codes || ncodes < 1 || ncodes > ORBG_MAX_CODES)
+        return fail(ORBG_EINVAL, "ncodes = %d outside [1, %d]", ncodes, ORBG_MAX_CODES);
+    if (batch > 0 && (!block_code || !row_offset || !llr || !codeword || !queries || !abandoned))
+        return fail(ORBG_EINVAL, "a device buffer is NULL");
+    std::vector<CodeEntry*> list(ncodes);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int i = 0; i < ncodes; ++i) {
+            if (codes[i] < 0 || codes[i] >= (int)g_registry.size() || !g_registry[codes[i]])
+                return fail(ORBG_EINVAL, "code id %d is not registered", codes[i]);
+            list[i] = g_registry[codes[i]];
+            if (list[i]->n > 256) return fail(ORBG_EINVAL, "mixed decodes take n <= 256 (code %d)", codes[i]);
+        }
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
+    for (int i = 0; i < ncodes; ++i)
+        if (list[i]->dev != dev) return fail(ORBG_EINVAL, "code id %d lives on another device", codes[i]);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    orbg::DecodeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.codes.ncodes = ncodes;
+    uint32_t col_base = 0;
+    for (int i = 0; i < ncodes; ++i) {
+        if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i]))) return rc;
+        col_base += (uint32_t)list[i]->n;
+    }
+    if (col_base > ORBG_MIXED_COLS)
+        return fail(ORBG_EINVAL, "the codes of one mixed decode may hold at most %d columns", ORBG_MIXED_COLS);
+    if (batch == 0) return ORBG_OK;
+    a.p = resolve_params(params, false);
+    Workspace* w = nullptr;
+    if ((rc = get_workspace(st, a.p.split_steps > 0 ? batch : 0, &w, &a.cus))) return rc;
+    a.mixed = true;
+    a.block_code = block_code;
+    a.row_off = row_offset;
+    a.llr = llr;
+    a.nblocks = batch;
+    a.budget = (uint32_t)budget;
+    a.order = nullptr;
+    a.cw = codeword;
+    a.queries = queries;
+    a.abandoned = abandoned;
+    a.ctrs = w->ctrs;
+    a.heavy = a.p.split_steps > 0 ? w->heavy : nullptr;
+    const hipError_t e = orbg::launch_decode(a, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "mixed decode launch failed: %s", hipGetErrorString(e));
+    return ORBG_OK;
 }
 
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)

@@ -3,27 +3,62 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#define ORBG_MAX_CODES 8       // codes one launch may mix
+#define ORBG_MIXED_COLS 2048   // packed columns of all codes of a mixed launch (sum of n)
+
 namespace orbg {
 
-struct DecodeArgs {
-    const float* llr;          // device, nblocks x n
-    int64_t nblocks;
-    int n;
+// One code of a launch (device pointers into the library's caches).
+struct CodeDesc {
+    int n;                     // code length
     int m;                     // n - k
-    const uint64_t* cols;      // device, n packed parity-check columns
-    const uint2* sched;        // device schedule entries (packed, see Schedule)
-    const uint32_t* bh;        // device per-batch count of ranks above 8
-    uint64_t slen;             // schedule entries
+    int nk;                    // keys per lane of the rank sort: power of two >= n / 64
     int rdepth;                // ranks whose columns are staged (<= 255)
-    uint64_t budget;
-    const uint8_t* order;      // device, nblocks x 64, or nullptr for plain order
-    uint8_t* cw;               // device, nblocks x n
-    uint64_t* queries;         // device, nblocks
-    uint8_t* abandoned;        // device, nblocks
-    int64_t max_workgroups;    // cap on the persistent grid (0 = no cap)
-    unsigned long long* work;  // device work counter (reset by the launch)
-    int chunk;                 // blocks taken per counter increment
+    uint32_t slen;             // schedule entries
+    uint32_t col_base;         // first column of this code in the launch's LDS column table
+    const uint64_t* cols;      // n packed parity-check columns
+    const uint2* sched;        // schedule entries for this n
+    const uint32_t* bh;        // per-batch count of ranks above 8
 };
+
+struct CodeTable {
+    int ncodes;
+    int pad;
+    CodeDesc c[ORBG_MAX_CODES];
+};
+
+// Launch shape (the autotuner's knobs).
+struct LaunchParams {
+    int wg_per_cu;             // light pass: one-wave workgroups per compute unit
+    int chunk;                 // blocks per work-counter increment (0 = about 16 per wave)
+    int split_steps;           // light pass stops a block after this many 64-query steps (0 = never)
+    int heavy_waves;           // waves that share one heavy block (4, 8 or 16)
+    int heavy_wg_per_cu;       // heavy pass: workgroups per compute unit
+};
+
+struct DecodeArgs {
+    CodeTable codes;
+    bool mixed;                // per-block code index and row offsets given
+    const uint8_t* block_code; // device, nblocks (mixed)
+    const int64_t* row_off;    // device, nblocks: element offset of the row in llr and codeword (mixed)
+    const float* llr;
+    int64_t nblocks;
+    uint32_t budget;
+    const uint8_t* order;      // device, nblocks x 64, or nullptr for plain order
+    uint8_t* cw;
+    uint64_t* queries;
+    uint8_t* abandoned;
+    unsigned long long* ctrs;  // device work counters (8 slices, heavy count, heavy next)
+    int64_t* heavy;            // device heavy-block list, capacity >= nblocks when splitting
+    int cus;                   // compute units of the device
+    LaunchParams p;
+};
+
+// Counter slots (u64 index, each on its own 256-byte line).
+#define ORBG_CTR_SLICE(x) ((x) * 32)
+#define ORBG_CTR_HEAVY_COUNT (8 * 32)
+#define ORBG_CTR_HEAVY_NEXT (9 * 32)
+#define ORBG_CTR_WORDS (10 * 32)
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream);
 

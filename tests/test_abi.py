@@ -42,3 +42,27 @@ def test_ordered_needs_n_at_least_12():
                                ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8),
                                ctypes.c_void_p(8), None)
     assert rc == -1 and "n >= 12" in L.orbg_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("workgroups_per_cu", 65, "workgroups_per_cu"), ("chunk", 5000, "chunk"), ("split_steps", -2, "split_steps"),
+    ("heavy_waves", 5, "heavy_waves"), ("heavy_workgroups_per_cu", 17, "heavy_workgroups_per_cu")])
+def test_launch_params_are_checked(field, value, msg):
+    L = binding.load()
+    H = np.zeros((6, 32), dtype=np.uint8)
+    p = binding.LaunchParams()
+    setattr(p, field, value)
+    rc = L.orbg_decode_ex(H.ctypes.data_as(ctypes.c_void_p), None, 32, 26, 100, 4, None, None, None, None,
+                          ctypes.byref(p), None)
+    assert rc == -1 and msg in L.orbg_last_error().decode()
+
+
+def test_mixed_rejects_unregistered_and_bad_counts():
+    L = binding.load()
+    ids = (ctypes.c_int * 1)(12345)
+    rc = L.orbg_decode_mixed(ids, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 100,
+                             ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None, None)
+    assert rc == -1 and "not registered" in L.orbg_last_error().decode()
+    rc = L.orbg_decode_mixed(ids, 9, None, None, None, 0, 100, None, None, None, None, None)
+    assert rc == -1 and "ncodes" in L.orbg_last_error().decode()
+    assert L.orbg_code_release(777) == -1

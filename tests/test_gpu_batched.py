@@ -1,0 +1,121 @@
+"""GPU: mixed-code persistent decodes, the heavy-block split and hipGraph replay.
+Every result is checked bit for bit against the oracle or against the plain
+single-code decode (itself parity-tested against the oracle)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2202_13951_amd import binding
+from synth import codes, mixed
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+NAMES = ["rlc64_52", "rlc128_116", "rlc256_240"]
+
+
+def _setup(N, ebn0, seed, dev):
+    HG = [codes.code(nm) for nm in NAMES]
+    llr, sent, bc, ro = mixed.mixed_llr([G for _, G in HG], [1, 2, 1], N, ebn0, seed)
+    ids = [binding.orbg_code_register(H) for H, _ in HG]
+    t = dict(llr=torch.from_numpy(llr).to(dev), bc=torch.from_numpy(bc).to(dev), ro=torch.from_numpy(ro).to(dev))
+    return HG, ids, llr, bc, ro, t
+
+
+def _run_mixed(ids, t, N, budget, params=None):
+    dev = t["llr"].device
+    cw = torch.zeros(t["llr"].numel(), dtype=torch.uint8, device=dev)
+    q = torch.zeros(N, dtype=torch.int64, device=dev)
+    ab = torch.zeros(N, dtype=torch.uint8, device=dev)
+    binding.orbg_decode_mixed(ids, t["bc"], t["ro"], t["llr"], budget, cw, q, ab, params=params)
+    torch.cuda.synchronize()
+    return cw.cpu().numpy(), q.cpu().numpy().astype(np.uint64), ab.cpu().numpy()
+
+
+def _rows(flat, ro, n, idx):
+    return flat[ro[idx][:, None] + np.arange(n)[None, :]]
+
+
+def test_mixed_matches_oracle(gpu_device):
+    print("mixed vs oracle", flush=True)
+    N, budget = 2400, 10 ** 6
+    HG, ids, llr, bc, ro, t = _setup(N, 4.0, 11, gpu_device)
+    cw, q, ab = _run_mixed(ids, t, N, budget)
+    for ci, (H, G) in enumerate(HG):
+        n = H.shape[1]
+        idx = np.nonzero(bc == ci)[0]
+        if ci == 2:
+            idx = idx[:300]
+        ocw, oq, oab = O.decode(H, _rows(llr, ro, n, idx), budget, THREADS)
+        assert (_rows(cw, ro, n, idx) == ocw).all(), NAMES[ci]
+        assert (q[idx] == oq).all() and (ab[idx] == oab).all(), NAMES[ci]
+    assert (q > 64 * 64).any()                      # the heavy pass took part
+
+
+@pytest.mark.parametrize("params", [
+    dict(split_steps=0), dict(split_steps=1), dict(split_steps=3, heavy_waves=4),
+    dict(split_steps=64, heavy_waves=16, heavy_workgroups_per_cu=1), dict(workgroups_per_cu=1, chunk=7),
+    dict(workgroups_per_cu=64, chunk=1, split_steps=8, heavy_waves=8, heavy_workgroups_per_cu=16)])
+def test_schedule_invariance(gpu_device, params):
+    """Any launch shape gives the same bits as the plain per-code decode."""
+    print(f"invariance {params}", flush=True)
+    N, budget = 6000, 10 ** 6
+    HG, ids, llr, bc, ro, t = _setup(N, 3.5, 12, gpu_device)
+    got = _run_mixed(ids, t, N, budget, binding.LaunchParams(**params))
+    for ci, (H, G) in enumerate(HG):
+        n = H.shape[1]
+        idx = np.nonzero(bc == ci)[0]
+        rows = torch.from_numpy(np.ascontiguousarray(_rows(llr, ro, n, idx))).to(gpu_device)
+        pcw, pq, pab = binding.orbg_decode(H, rows, budget)
+        torch.cuda.synchronize()
+        assert (_rows(got[0], ro, n, idx) == pcw.cpu().numpy()).all()
+        assert (got[1][idx] == pq.cpu().numpy().astype(np.uint64)).all()
+        assert (got[2][idx] == pab.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("split,waves", [(0, 8), (1, 4), (2, 16), (64, 8), (300, 4)])
+def test_single_code_split_invariance(gpu_device, split, waves):
+    print(f"single split {split} {waves}", flush=True)
+    H, G = codes.code("bch127_113")
+    from synth import channel
+    llr, _ = channel.awgn_llr(G, 20000, 4.0, seed=77)
+    x = torch.from_numpy(llr).to(gpu_device)
+    ref = [v.cpu().numpy() for v in binding.orbg_decode_ex(H, x, 10 ** 5, params=binding.LaunchParams(split_steps=0))]
+    got = [v.cpu().numpy() for v in binding.orbg_decode_ex(
+        H, x, 10 ** 5, params=binding.LaunchParams(split_steps=split, heavy_waves=waves))]
+    for a, b in zip(ref, got):
+        assert (a == b).all()
+    sample = np.arange(0, 20000, 40)
+    ocw, oq, oab = O.decode(H, llr[sample], 10 ** 5, THREADS)
+    assert (got[0][sample] == ocw).all() and (got[1][sample].astype(np.uint64) == oq).all()
+
+
+def test_hip_graph_replay(gpu_device):
+    """The mixed decode (counter reset, light pass, heavy pass) captured in a graph:
+    every replay, with eager work in between, equals the eager result."""
+    print("graph replay", flush=True)
+    N, budget = 3000, 10 ** 6
+    HG, ids, llr, bc, ro, t = _setup(N, 3.5, 13, gpu_device)
+    eager = _run_mixed(ids, t, N, budget)
+    s = torch.cuda.Stream()
+    cw = torch.zeros(t["llr"].numel(), dtype=torch.uint8, device=gpu_device)
+    q = torch.zeros(N, dtype=torch.int64, device=gpu_device)
+    ab = torch.zeros(N, dtype=torch.uint8, device=gpu_device)
+    with torch.cuda.stream(s):                        # warm-up: work space for this stream
+        binding.orbg_decode_mixed(ids, t["bc"], t["ro"], t["llr"], budget, cw, q, ab)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        binding.orbg_decode_mixed(ids, t["bc"], t["ro"], t["llr"], budget, cw, q, ab)
+    for rep in range(3):
+        cw.fill_(7)
+        q.fill_(-1)
+        ab.fill_(9)
+        _run_mixed(ids, t, N, budget)                 # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert (cw.cpu().numpy() == eager[0]).all(), rep
+        assert (q.cpu().numpy().astype(np.uint64) == eager[1]).all(), rep
+        assert (ab.cpu().numpy() == eager[2]).all(), rep
