@@ -7,7 +7,7 @@ workgroups per CU.  Each candidate is timed with HIP events on the stream the
 decode runs on (median of a few launches of the caller's workload).  The
 decoded bits do not depend on the launch shape, so tuning never changes
 results.  Best shapes are cached in tuned.json next to this file, keyed by
-device name and workload name.
+architecture and compute-unit count (e.g. gfx950-256cu) and workload name.
 
   python -m paper_2202_13951_amd.autotune --workload bch127 --out tuned.json
 """
@@ -75,8 +75,11 @@ def tune(run, start: dict | None = None, rounds: int = 2, reps: int = 3, log=Non
 
 
 def device_name() -> str:
+    """Architecture and compute-unit count, e.g. gfx950-256cu (marketing names vary
+    with the driver's device table)."""
     import torch
-    return torch.cuda.get_device_name(torch.cuda.current_device())
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{p.gcnArchName.split(':')[0]}-{p.multi_processor_count}cu"
 
 
 def load_tuned(workload: str, path: str = CACHE):
