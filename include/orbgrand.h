@@ -149,6 +149,59 @@ int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code,
  */
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream);
 
+/*
+ * Learned batch-order proposal (an addition to the paper's method, used through
+ * orbg_decode_ordered; the basic ORBGRAND order stays the fallback after the 64
+ * reordered batches, and every decision is still a parity-checked codeword).
+ *
+ * Network: 128 -> 256 -> 256 -> 64 with ReLU; weights in BF16, accumulation in
+ * FP32 on the matrix cores, activations stored in BF16, biases in FP32.
+ * Parameters (caller-owned DEVICE buffers):
+ *   w   FP32 [ORBG_MLP_PARAMS] masters, flat: W1 [256 x 128], b1 [256],
+ *       W2 [256 x 256], b2 [256], W3 [64 x 256], b3 [64] (output x input, row-major);
+ *   wb  BF16 bits [ORBG_MLP_PARAMS], the same layout rounded to nearest even;
+ *   wt  BF16 bits [ORBG_MLP_TPARAMS], W1, W2, W3 transposed (input x output), in order;
+ *   m, v FP32 [ORBG_MLP_PARAMS] Adam moments.
+ * Calls that run the network take a DEVICE work space of at least
+ * orbg_mlp_workspace_bytes(batch) bytes (1 <= batch <= 2^20); it holds the
+ * activations and gradient partial sums of one call.  All calls are
+ * asynchronous on `stream`.
+ */
+#define ORBG_MLP_PARAMS 115264
+#define ORBG_MLP_TPARAMS 114688
+
+/* Work space bytes for `batch` rows (-1 if batch is out of range). */
+int64_t orbg_mlp_workspace_bytes(int64_t batch);
+
+/* Features of `batch` blocks of length n = 128 (DEVICE llr rows): each block's
+ * |LLR| values sorted ascending (the ordered reliability curve of Sec. III-A),
+ * times 1/8, rounded to BF16 -> x [batch x 128] BF16 bits. */
+int orbg_mlp_features(const float* llr, int n, int64_t batch, uint16_t* x, void* stream);
+
+/* wb and wt from the FP32 masters w. */
+int orbg_mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, void* stream);
+
+/* logits [batch x 64] FP32 of features x [batch x 128]. */
+int orbg_mlp_forward(const float* w, const uint16_t* wb, const uint16_t* x, int64_t batch, float* logits,
+                     void* workspace, int64_t workspace_bytes, void* stream);
+
+/* Mean softmax cross-entropy of the logits against labels (DEVICE int32 in
+ * 0..63: the batch of the plain decoder's first hit) into *loss (DEVICE FP32),
+ * and its gradient with respect to every parameter into grads (FP32, layout of w). */
+int orbg_mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, const uint16_t* x,
+                      const int32_t* labels, int64_t batch, float* grads, float* loss, void* workspace,
+                      int64_t workspace_bytes, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step counts
+ * from 1) on w, m, v; refreshes wb and wt. */
+int orbg_mlp_adam(float* w, float* m, float* v, const float* grads, float lr, int step, uint16_t* wb,
+                  uint16_t* wt, void* stream);
+
+/* Batch order for orbg_decode_ordered: each row of 64 logits sorted by
+ * decreasing value, ties (and +0/-0) to the lower index, NaN last -> order
+ * [batch x 64] u8. */
+int orbg_mlp_order(const float* logits, int64_t batch, uint8_t* order, void* stream);
+
 /* Message describing the calling thread's last non-OK status ("" if none). */
 const char* orbg_last_error(void);
 

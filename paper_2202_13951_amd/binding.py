@@ -59,6 +59,20 @@ def load():
     L.orbg_code_release.restype = ci
     L.orbg_decode_mixed.argtypes = [vp, ci, vp, vp, vp, i64, u64, vp, vp, vp, vp, vp]
     L.orbg_decode_mixed.restype = ci
+    L.orbg_mlp_workspace_bytes.argtypes = [i64]
+    L.orbg_mlp_workspace_bytes.restype = i64
+    L.orbg_mlp_features.argtypes = [vp, ci, i64, vp, vp]
+    L.orbg_mlp_features.restype = ci
+    L.orbg_mlp_prepare.argtypes = [vp, vp, vp, vp]
+    L.orbg_mlp_prepare.restype = ci
+    L.orbg_mlp_forward.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp]
+    L.orbg_mlp_forward.restype = ci
+    L.orbg_mlp_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, i64, vp]
+    L.orbg_mlp_backward.restype = ci
+    L.orbg_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_float, ci, vp, vp, vp]
+    L.orbg_mlp_adam.restype = ci
+    L.orbg_mlp_order.argtypes = [vp, i64, vp, vp]
+    L.orbg_mlp_order.restype = ci
     L.orbg_schedule_export.argtypes = [ci, u64, vp, vp]
     L.orbg_schedule_export.restype = ci
     L.orbg_last_error.argtypes = []
@@ -191,3 +205,48 @@ def orbg_schedule_export(n: int, count: int, stream=None) -> np.ndarray:
                                      _stream_ptr(stream))
     _check("orbg_schedule_export", rc)
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned batch-order proposal (tensors: torch CUDA, contiguous)
+# ---------------------------------------------------------------------------
+MLP_PARAMS = 115264
+MLP_TPARAMS = 114688
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def orbg_mlp_workspace_bytes(batch: int) -> int:
+    return int(load().orbg_mlp_workspace_bytes(int(batch)))
+
+
+def orbg_mlp_features(llr, x, stream=None):
+    """x (int16 [N,128], BF16 bits) <- sorted |llr| / 8 of llr (float32 [N,128])."""
+    N, n = llr.shape
+    _check("orbg_mlp_features", load().orbg_mlp_features(_p(llr), n, N, _p(x), _stream_ptr(stream)))
+
+
+def orbg_mlp_prepare(w, wb, wt, stream=None):
+    _check("orbg_mlp_prepare", load().orbg_mlp_prepare(_p(w), _p(wb), _p(wt), _stream_ptr(stream)))
+
+
+def orbg_mlp_forward(w, wb, x, logits, workspace, stream=None):
+    _check("orbg_mlp_forward", load().orbg_mlp_forward(_p(w), _p(wb), _p(x), x.shape[0], _p(logits), _p(workspace),
+                                                       workspace.numel(), _stream_ptr(stream)))
+
+
+def orbg_mlp_backward(w, wb, wt, x, labels, grads, loss, workspace, stream=None):
+    _check("orbg_mlp_backward", load().orbg_mlp_backward(_p(w), _p(wb), _p(wt), _p(x), _p(labels), x.shape[0],
+                                                         _p(grads), _p(loss), _p(workspace), workspace.numel(),
+                                                         _stream_ptr(stream)))
+
+
+def orbg_mlp_adam(w, m, v, grads, lr: float, step: int, wb, wt, stream=None):
+    _check("orbg_mlp_adam", load().orbg_mlp_adam(_p(w), _p(m), _p(v), _p(grads), float(lr), int(step), _p(wb),
+                                                 _p(wt), _stream_ptr(stream)))
+
+
+def orbg_mlp_order(logits, order, stream=None):
+    _check("orbg_mlp_order", load().orbg_mlp_order(_p(logits), logits.shape[0], _p(order), _stream_ptr(stream)))

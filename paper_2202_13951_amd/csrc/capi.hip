@@ -16,6 +16,7 @@
 
 #include "orbg_internal.h"
 #include "orbg_kernels.h"
+#include "orbg_mlp.h"
 
 namespace {
 
@@ -409,6 +410,86 @@ int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)
     (void)hipFree(d_out);
     if (!ok) return fail(ORBG_EHIP, "schedule export failed");
     return ORBG_OK;
+}
+
+int64_t orbg_mlp_workspace_bytes(int64_t batch)
+{
+    if (batch < 0 || batch > MLP_BATCH_MAX) return -1;
+    return orbg::mlp_carve(nullptr, batch).bytes;
+}
+
+int orbg_mlp_features(const float* llr, int n, int64_t batch, uint16_t* x, void* stream)
+{
+    g_err.clear();
+    if (n != MLP_IN) return fail(ORBG_EINVAL, "features take n = %d (got %d)", MLP_IN, n);
+    if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
+    if (batch > 0 && (!llr || !x)) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_features(llr, batch, x, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "features launch failed: %s", hipGetErrorString(e));
+}
+
+int orbg_mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, void* stream)
+{
+    g_err.clear();
+    if (!w || !wb || !wt) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_prepare(w, wb, wt, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "prepare launch failed: %s", hipGetErrorString(e));
+}
+
+static int mlp_check(int64_t batch, void* workspace, int64_t workspace_bytes)
+{
+    if (batch < 0 || batch > MLP_BATCH_MAX)
+        return fail(ORBG_EINVAL, "batch = %lld outside [0, %d]", (long long)batch, MLP_BATCH_MAX);
+    if (batch > 0 && (!workspace || workspace_bytes < orbg::mlp_carve(nullptr, batch).bytes))
+        return fail(ORBG_EINVAL, "work space of %lld bytes is smaller than the %lld needed", (long long)workspace_bytes,
+                    (long long)orbg::mlp_carve(nullptr, batch).bytes);
+    return ORBG_OK;
+}
+
+int orbg_mlp_forward(const float* w, const uint16_t* wb, const uint16_t* x, int64_t batch, float* logits,
+                     void* workspace, int64_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    int rc = mlp_check(batch, workspace, workspace_bytes);
+    if (rc) return rc;
+    if (batch > 0 && (!w || !wb || !x || !logits)) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_forward(w, wb, x, batch, logits, orbg::mlp_carve(workspace, batch),
+                                           reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "forward launch failed: %s", hipGetErrorString(e));
+}
+
+int orbg_mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, const uint16_t* x,
+                      const int32_t* labels, int64_t batch, float* grads, float* loss, void* workspace,
+                      int64_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    int rc = mlp_check(batch, workspace, workspace_bytes);
+    if (rc) return rc;
+    if (batch < 1) return fail(ORBG_EINVAL, "the backward needs batch >= 1");
+    if (!w || !wb || !wt || !x || !labels || !grads || !loss) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_backward(w, wb, wt, x, labels, batch, grads, loss,
+                                            orbg::mlp_carve(workspace, batch), reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "backward launch failed: %s", hipGetErrorString(e));
+}
+
+int orbg_mlp_adam(float* w, float* m, float* v, const float* grads, float lr, int step, uint16_t* wb, uint16_t* wt,
+                  void* stream)
+{
+    g_err.clear();
+    if (!w || !m || !v || !grads || !wb || !wt) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    if (!(lr > 0.f) || lr > 1.f) return fail(ORBG_EINVAL, "lr = %g outside (0, 1]", (double)lr);
+    if (step < 1) return fail(ORBG_EINVAL, "step = %d (steps count from 1)", step);
+    const hipError_t e = orbg::mlp_adam(w, m, v, grads, lr, step, wb, wt, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "adam launch failed: %s", hipGetErrorString(e));
+}
+
+int orbg_mlp_order(const float* logits, int64_t batch, uint8_t* order, void* stream)
+{
+    g_err.clear();
+    if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
+    if (batch > 0 && (!logits || !order)) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_order(logits, batch, order, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "order launch failed: %s", hipGetErrorString(e));
 }
 
 const char* orbg_last_error(void) { return g_err.c_str(); }

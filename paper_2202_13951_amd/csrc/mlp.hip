@@ -1,0 +1,382 @@
+// Learned batch-order proposal: a 128 -> 256 -> 256 -> 64 ReLU network in BF16
+// with FP32 accumulation on the matrix cores, its backward pass and Adam.
+//
+// Input of the network: a block's reliabilities |LLR_i| sorted ascending (the
+// ordered reliability curve of Sec. III-A), scaled by 1/8 and rounded to BF16.
+// Output: 64 logits, one per batch of 64 consecutive patterns of the basic
+// ORBGRAND order; the decoder tests batches by decreasing logit
+// (orbg_decode_ordered) and falls back to the plain order after them.
+//
+// Parameters (FP32 masters, flat): W1 [256 x 128], b1 [256], W2 [256 x 256],
+// b2 [256], W3 [64 x 256], b3 [64] (output x input, row-major).  The forward
+// uses BF16 copies of the weights (same layout); the backward also uses BF16
+// transposed copies W1t [128 x 256], W2t [256 x 256], W3t [256 x 64].
+//
+// GEMMs: v_mfma_f32_16x16x16_bf16 tiles, a 64 x 64 output tile per 256-thread
+// workgroup (each wave 32 x 32 = 2 x 2 MFMA tiles), K in steps of 16 with
+// fragments read straight from global memory (operands are small and stay in
+// L2).  Weight gradients reduce over the batch: split-K partials in FP32 and a
+// deterministic reduction.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "orbg_device.h"
+#include "orbg_mlp.h"
+
+namespace orbg {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                 // nearest, ties to even
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// ---------------------------------------------------------------------------
+// Features: sorted |LLR| / 8 in BF16, one wave per block (n = 128).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ llr, int64_t batch,
+                                                       uint16_t* __restrict__ x)
+{
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
+    if (b >= batch) return;
+    uint32_t key[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) key[j] = __float_as_uint(llr[b * MLP_IN + j * ORBG_WAVE + lane]) & 0x7fffffffu;
+    bitonic_sort<2, uint32_t>(key);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) x[b * MLP_IN + lane * 2 + j] = f32_to_bf16(__uint_as_float(key[j]) * 0.125f);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM C[M x N] = sum_k A(i, k) B(k, j); A(i, k) = A[i * a_i + k * a_k],
+// B(k, j) = B[k * b_k + j * b_j] (BF16).  AK / BK: unit stride along k.
+// ---------------------------------------------------------------------------
+enum { EPI_HIDDEN = 0, EPI_LOGITS = 1, EPI_MASKED = 2, EPI_PARTIAL = 3 };
+
+// Four consecutive-k values of one row (A) or column (B); `nk` of them exist
+// (0..4).  UNIT: unit stride, then the caller guarantees nk is 0 or 4.
+template <bool UNIT>
+__device__ __forceinline__ s4v load_frag(const uint16_t* __restrict__ p, int64_t stride, int nk)
+{
+    s4v r = {0, 0, 0, 0};
+    if (nk <= 0) return r;
+    if (UNIT) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        r.x = (short)(v.x & 0xffffu); r.y = (short)(v.x >> 16);
+        r.z = (short)(v.y & 0xffffu); r.w = (short)(v.y >> 16);
+    } else {
+        r.x = (short)p[0];
+        if (nk > 1) r.y = (short)p[stride];
+        if (nk > 2) r.z = (short)p[2 * stride];
+        if (nk > 3) r.w = (short)p[3 * stride];
+    }
+    return r;
+}
+
+template <bool AK, bool BK, int EPI>
+__global__ void __launch_bounds__(256)
+gemm_kernel(const uint16_t* __restrict__ A, int64_t a_i, int64_t a_k, const uint16_t* __restrict__ B, int64_t b_k,
+            int64_t b_j, int M, int N, int K, int kchunk, const float* __restrict__ bias,
+            void* __restrict__ out, int64_t ldo, const uint16_t* __restrict__ mask, int64_t ldm)
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x / ORBG_WAVE;
+    const int i0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int j0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+    const int r = lane & 15, q = lane >> 4;
+    f4v acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = (f4v){0.f, 0.f, 0.f, 0.f};
+    for (int k = kb; k < ke; k += 16) {
+        const int kk = k + 4 * q;                   // this lane's 4 consecutive k
+        const int nk = min(4, ke - kk);             // how many of them exist (<= 0: none)
+        s4v fa[2], fb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int i = i0 + a * 16 + r;
+            fa[a] = load_frag<AK>(A + (int64_t)i * a_i + (int64_t)kk * a_k, a_k, i < M ? nk : 0);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int j = j0 + c * 16 + r;
+            fb[c] = load_frag<BK>(B + (int64_t)j * b_j + (int64_t)kk * b_k, b_k, j < N ? nk : 0);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[c], acc[a][c], 0, 0, 0);
+    }
+    // lane holds D[4q + t][r] of each 16 x 16 tile, t = 0..3
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = i0 + a * 16 + 4 * q + t;
+                const int j = j0 + c * 16 + r;
+                if (i >= M || j >= N) continue;
+                const float v = acc[a][c][t];
+                if (EPI == EPI_HIDDEN) {
+                    reinterpret_cast<uint16_t*>(out)[(int64_t)i * ldo + j] = f32_to_bf16(fmaxf(v + bias[j], 0.f));
+                } else if (EPI == EPI_LOGITS) {
+                    reinterpret_cast<float*>(out)[(int64_t)i * ldo + j] = v + bias[j];
+                } else if (EPI == EPI_MASKED) {
+                    const bool on = mask[(int64_t)i * ldm + j] != 0;      // ReLU output > 0
+                    reinterpret_cast<uint16_t*>(out)[(int64_t)i * ldo + j] = on ? f32_to_bf16(v) : (uint16_t)0;
+                } else {
+                    reinterpret_cast<float*>(out)[(int64_t)blockIdx.z * M * N + (int64_t)i * N + j] = v;
+                }
+            }
+}
+
+// out[e] = sum over s < splits of part[s * count + e]
+__global__ void reduce_partials_kernel(const float* __restrict__ part, int splits, int64_t count,
+                                       float* __restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * count + e];
+    out[e] = s;
+}
+
+// Column sums of a BF16 [rows x cols] matrix: part[z * cols + j] over rows [z*chunk, ...).
+__global__ void colsum_kernel(const uint16_t* __restrict__ g, int64_t rows, int cols, int64_t chunk,
+                              float* __restrict__ part)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.y;
+    if (j >= cols) return;
+    const int64_t rb = (int64_t)z * chunk, re = min(rows, rb + chunk);
+    float s = 0.f;
+    for (int64_t i = rb; i < re; ++i) s += bf16_to_f32(g[i * cols + j]);
+    part[(int64_t)z * cols + j] = s;
+}
+
+// Softmax cross-entropy, one wave per row (lane = class): dl = (softmax - onehot) / B
+// in BF16, per-row loss into rowloss.
+__global__ void __launch_bounds__(256) softmax_ce_kernel(const float* __restrict__ logits,
+                                                         const int32_t* __restrict__ labels, int64_t batch,
+                                                         uint16_t* __restrict__ dl, float* __restrict__ rowloss)
+{
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
+    if (b >= batch) return;
+    const float v = logits[b * MLP_OUT + lane];
+    float mx = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) mx = fmaxf(mx, __shfl_xor(mx, d, ORBG_WAVE));
+    const float e = __expf(v - mx);
+    float s = e;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) s += __shfl_xor(s, d, ORBG_WAVE);
+    const int lab = labels[b];
+    const float p = e / s;
+    dl[b * MLP_OUT + lane] = f32_to_bf16((p - (lane == lab ? 1.f : 0.f)) / (float)batch);
+    const float vl = __shfl(v, lab & 63, ORBG_WAVE);
+    if (lane == 0) rowloss[b] = (__logf(s) + mx - vl);
+}
+
+__global__ void sum_kernel(const float* __restrict__ x, int64_t count, float scale, float* __restrict__ out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// BF16 copies (and transposed copies of the weight matrices) of FP32 masters.
+__device__ __forceinline__ void write_copies(int64_t p, float w, uint16_t* __restrict__ wb, uint16_t* __restrict__ wt)
+{
+    const uint16_t h = f32_to_bf16(w);
+    wb[p] = h;
+    if (p < MLP_OFF_B1) {                                           // W1 [256 x 128]
+        const int64_t rr = p / MLP_IN, cc = p % MLP_IN;
+        wt[MLP_T_W1 + cc * MLP_HID + rr] = h;
+    } else if (p >= MLP_OFF_W2 && p < MLP_OFF_B2) {                 // W2 [256 x 256]
+        const int64_t qq = p - MLP_OFF_W2, rr = qq / MLP_HID, cc = qq % MLP_HID;
+        wt[MLP_T_W2 + cc * MLP_HID + rr] = h;
+    } else if (p >= MLP_OFF_W3 && p < MLP_OFF_B3) {                 // W3 [64 x 256]
+        const int64_t qq = p - MLP_OFF_W3, rr = qq / MLP_HID, cc = qq % MLP_HID;
+        wt[MLP_T_W3 + cc * MLP_OUT + rr] = h;
+    }
+}
+
+__global__ void prepare_kernel(const float* __restrict__ w, uint16_t* __restrict__ wb, uint16_t* __restrict__ wt)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < MLP_NPARAM) write_copies(p, w[p], wb, wt);
+}
+
+__global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, float lr, float beta1, float beta2, float eps, float c1,
+                            float c2, uint16_t* __restrict__ wb, uint16_t* __restrict__ wt)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= MLP_NPARAM) return;
+    const float gg = g[p];
+    const float mm = beta1 * m[p] + (1.f - beta1) * gg;
+    const float vv = beta2 * v[p] + (1.f - beta2) * gg * gg;
+    m[p] = mm;
+    v[p] = vv;
+    const float ww = w[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    w[p] = ww;
+    write_copies(p, ww, wb, wt);
+}
+
+// Batch order: decreasing logit, ties (and +-0) to the lower index, NaN last.
+__global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ logits, int64_t batch,
+                                                    uint8_t* __restrict__ order)
+{
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
+    if (b >= batch) return;
+    const float f = logits[b * MLP_OUT + lane] + 0.0f;          // -0 -> +0
+    const uint32_t u = __float_as_uint(f);
+    const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+    const uint32_t key = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f
+    int rank = 0;
+    for (int mm = 0; mm < 64; ++mm) {
+        const uint32_t km = __shfl(key, mm, ORBG_WAVE);
+        rank += (km > key) || (km == key && mm < lane);
+    }
+    order[b * MLP_OUT + rank] = (uint8_t)lane;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------
+static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+MlpWorkspace mlp_carve(void* base, int64_t batch)
+{
+    MlpWorkspace w;
+    unsigned char* p = reinterpret_cast<unsigned char*>(base);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += align256(bytes); return r; };
+    const int splits = (int)((batch + MLP_KCHUNK - 1) / MLP_KCHUNK);
+    w.h1 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.h2 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.logits = (float*)take(batch * MLP_OUT * 4);
+    w.dl = (uint16_t*)take(batch * MLP_OUT * 2);
+    w.dz2 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.dz1 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.part = (float*)take((int64_t)splits * MLP_HID * MLP_HID * 4);
+    w.rowloss = (float*)take(batch * 4);
+    w.splits = splits;
+    w.bytes = o;
+    return w;
+}
+
+template <bool AK, bool BK, int EPI>
+static void gemm(const uint16_t* A, int64_t a_i, int64_t a_k, const uint16_t* B, int64_t b_k, int64_t b_j, int M,
+                 int N, int K, int splits, int kchunk, const float* bias, void* out, int64_t ldo,
+                 const uint16_t* mask, int64_t ldm, hipStream_t st)
+{
+    dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+    gemm_kernel<AK, BK, EPI><<<grid, 256, 0, st>>>(A, a_i, a_k, B, b_k, b_j, M, N, K, kchunk, bias, out, ldo,
+                                                   mask, ldm);
+}
+
+hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st)
+{
+    if (batch > 0) features_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(llr, batch, x);
+    return hipGetLastError();
+}
+
+hipError_t mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, hipStream_t st)
+{
+    prepare_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(w, wb, wt);
+    return hipGetLastError();
+}
+
+// Forward; activations h1, h2 kept in the work space (for the backward).
+hipError_t mlp_forward(const float* w, const uint16_t* wb, const uint16_t* x, int64_t batch, float* logits,
+                       const MlpWorkspace& ws, hipStream_t st)
+{
+    if (batch <= 0) return hipSuccess;
+    const int Bm = (int)batch;
+    gemm<true, true, EPI_HIDDEN>(x, MLP_IN, 1, wb + MLP_OFF_W1, 1, MLP_IN, Bm, MLP_HID, MLP_IN, 1, MLP_IN,
+                                 w + MLP_OFF_B1, ws.h1, MLP_HID, nullptr, 0, st);
+    gemm<true, true, EPI_HIDDEN>(ws.h1, MLP_HID, 1, wb + MLP_OFF_W2, 1, MLP_HID, Bm, MLP_HID, MLP_HID, 1, MLP_HID,
+                                 w + MLP_OFF_B2, ws.h2, MLP_HID, nullptr, 0, st);
+    gemm<true, true, EPI_LOGITS>(ws.h2, MLP_HID, 1, wb + MLP_OFF_W3, 1, MLP_HID, Bm, MLP_OUT, MLP_HID, 1, MLP_HID,
+                                 w + MLP_OFF_B3, logits, MLP_OUT, nullptr, 0, st);
+    return hipGetLastError();
+}
+
+// Backward: forward, softmax cross-entropy, gradients of all parameters, mean loss.
+hipError_t mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, const uint16_t* x,
+                        const int32_t* labels, int64_t batch, float* grads, float* loss, const MlpWorkspace& ws,
+                        hipStream_t st)
+{
+    if (batch <= 0) return hipSuccess;
+    hipError_t e = mlp_forward(w, wb, x, batch, ws.logits, ws, st);
+    if (e != hipSuccess) return e;
+    const int Bm = (int)batch;
+    const int S = ws.splits;
+    softmax_ce_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(ws.logits, labels, batch, ws.dl, ws.rowloss);
+    sum_kernel<<<1, 256, 0, st>>>(ws.rowloss, batch, 1.0f / (float)batch, loss);
+    // layer 3: dW3 = dl^T h2, db3 = colsum(dl), dz2 = (dl W3) * [h2 > 0]
+    gemm<false, false, EPI_PARTIAL>(ws.dl, 1, MLP_OUT, ws.h2, MLP_HID, 1, MLP_OUT, MLP_HID, Bm, S, MLP_KCHUNK, nullptr,
+                                    ws.part, 0, nullptr, 0, st);
+    reduce_partials_kernel<<<(MLP_OUT * MLP_HID + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_OUT * MLP_HID,
+                                                                           grads + MLP_OFF_W3);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dl, batch, MLP_OUT, MLP_KCHUNK, ws.part);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_OUT, grads + MLP_OFF_B3);
+    gemm<true, true, EPI_MASKED>(ws.dl, MLP_OUT, 1, wt + MLP_T_W3, 1, MLP_OUT, Bm, MLP_HID, MLP_OUT, 1, MLP_OUT,
+                                 nullptr, ws.dz2, MLP_HID, ws.h2, MLP_HID, st);
+    // layer 2
+    gemm<false, false, EPI_PARTIAL>(ws.dz2, 1, MLP_HID, ws.h1, MLP_HID, 1, MLP_HID, MLP_HID, Bm, S, MLP_KCHUNK,
+                                    nullptr, ws.part, 0, nullptr, 0, st);
+    reduce_partials_kernel<<<(MLP_HID * MLP_HID + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_HID * MLP_HID,
+                                                                           grads + MLP_OFF_W2);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz2, batch, MLP_HID, MLP_KCHUNK, ws.part);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_HID, grads + MLP_OFF_B2);
+    gemm<true, true, EPI_MASKED>(ws.dz2, MLP_HID, 1, wt + MLP_T_W2, 1, MLP_HID, Bm, MLP_HID, MLP_HID, 1, MLP_HID,
+                                 nullptr, ws.dz1, MLP_HID, ws.h1, MLP_HID, st);
+    // layer 1
+    gemm<false, false, EPI_PARTIAL>(ws.dz1, 1, MLP_HID, x, MLP_IN, 1, MLP_HID, MLP_IN, Bm, S, MLP_KCHUNK, nullptr,
+                                    ws.part, 0, nullptr, 0, st);
+    reduce_partials_kernel<<<(MLP_HID * MLP_IN + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_HID * MLP_IN,
+                                                                          grads + MLP_OFF_W1);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz1, batch, MLP_HID, MLP_KCHUNK, ws.part);
+    reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_HID, grads + MLP_OFF_B1);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, float lr, int step, uint16_t* wb, uint16_t* wt,
+                    hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    adam_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, st>>>(w, m, v, g, lr, b1, b2, eps, c1, c2, wb, wt);
+    return hipGetLastError();
+}
+
+hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st)
+{
+    if (batch > 0) order_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(logits, batch, order);
+    return hipGetLastError();
+}
+
+}  // namespace orbg

@@ -57,8 +57,8 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // lane and larger ones across lanes (lane distance d / NK).  Keys must be
 // distinct except for padding.  A compare-exchange is one 64-bit compare, a
 // lane-mask XOR with the stage's direction and two selects.
-template <int NK>
-__device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
+template <int NK, typename KEY = uint64_t>
+__device__ __forceinline__ void bitonic_sort(KEY (&key)[NK])
 {
     const int lane = lane_id();
 #pragma unroll
@@ -71,7 +71,7 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
                     if ((j & d) == 0) {
                         // ascending iff bit `size` of e = lane * NK + j is clear
                         const bool desc = ((lane * NK + j) & size) != 0;
-                        const uint64_t a = key[j], b = key[j | d];
+                        const KEY a = key[j], b = key[j | d];
                         const bool sw = (a > b) != desc;
                         key[j] = sw ? b : a;
                         key[j | d] = sw ? a : b;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[NK])
                 const bool keep_min = ((lane & ld) == 0) == (((lane * NK) & size) == 0);
 #pragma unroll
                 for (int j = 0; j < NK; ++j) {
-                    const uint64_t p = __shfl_xor(key[j], ld, ORBG_WAVE);
+                    const KEY p = __shfl_xor(key[j], ld, ORBG_WAVE);
                     const bool take_p = (p < key[j]) == keep_min;
                     key[j] = take_p ? p : key[j];
                 }

@@ -1,0 +1,55 @@
+// Learned-proposal network: sizes, parameter layout, launchers (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MLP_IN 128
+#define MLP_HID 256
+#define MLP_OUT 64
+// flat FP32 / BF16 parameter layout (output x input, row-major)
+#define MLP_OFF_W1 0
+#define MLP_OFF_B1 (MLP_OFF_W1 + MLP_HID * MLP_IN)
+#define MLP_OFF_W2 (MLP_OFF_B1 + MLP_HID)
+#define MLP_OFF_B2 (MLP_OFF_W2 + MLP_HID * MLP_HID)
+#define MLP_OFF_W3 (MLP_OFF_B2 + MLP_HID)
+#define MLP_OFF_B3 (MLP_OFF_W3 + MLP_OUT * MLP_HID)
+#define MLP_NPARAM (MLP_OFF_B3 + MLP_OUT)
+// transposed BF16 weight copies (input x output)
+#define MLP_T_W1 0
+#define MLP_T_W2 (MLP_T_W1 + MLP_IN * MLP_HID)
+#define MLP_T_W3 (MLP_T_W2 + MLP_HID * MLP_HID)
+#define MLP_NTRANS (MLP_T_W3 + MLP_HID * MLP_OUT)
+#define MLP_KCHUNK 1024      // batch rows per split of a weight-gradient GEMM
+#define MLP_BATCH_MAX (1 << 20)
+
+namespace orbg {
+
+struct MlpWorkspace {
+    uint16_t* h1;
+    uint16_t* h2;
+    float* logits;
+    uint16_t* dl;
+    uint16_t* dz2;
+    uint16_t* dz1;
+    float* part;
+    float* rowloss;
+    int splits;
+    int64_t bytes;
+};
+
+// Carves the work space of a `batch`-row call out of `base` (base may be
+// nullptr to only compute .bytes).
+MlpWorkspace mlp_carve(void* base, int64_t batch);
+
+hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st);
+hipError_t mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, hipStream_t st);
+hipError_t mlp_forward(const float* w, const uint16_t* wb, const uint16_t* x, int64_t batch, float* logits,
+                       const MlpWorkspace& ws, hipStream_t st);
+hipError_t mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, const uint16_t* x,
+                        const int32_t* labels, int64_t batch, float* grads, float* loss, const MlpWorkspace& ws,
+                        hipStream_t st);
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, float lr, int step, uint16_t* wb, uint16_t* wt,
+                    hipStream_t st);
+hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st);
+
+}  // namespace orbg

@@ -61,3 +61,30 @@ def awgn_llr_torch(G: np.ndarray, n_blocks: int, ebn0_db: float, seed: int, devi
         llr[s:e] = 2.0 * y / float(s2)
         cws[s:e] = c.to(torch.uint8)
     return llr, cws
+
+
+def awgn_llr_torch_snr_range(G: np.ndarray, n_blocks: int, ebn0_lo: float, ebn0_hi: float, seed: int, device):
+    """torch on `device`: each block draws its own Eb/N0 uniformly in [lo, hi] dB.
+    Returns (llr float32 [N, n], codewords uint8 [N, n], ebn0 float32 [N])."""
+    import torch
+    k, n = G.shape
+    R = k / n
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    Gt = torch.as_tensor(G, dtype=torch.float32, device=device)
+    llr = torch.empty((n_blocks, n), dtype=torch.float32, device=device)
+    cws = torch.empty((n_blocks, n), dtype=torch.uint8, device=device)
+    snr = torch.empty(n_blocks, dtype=torch.float32, device=device)
+    chunk = 1 << 18
+    for s in range(0, n_blocks, chunk):
+        e = min(n_blocks, s + chunk)
+        eb = ebn0_lo + (ebn0_hi - ebn0_lo) * torch.rand(e - s, generator=gen, device=device)
+        s2 = 1.0 / (2.0 * R * torch.pow(10.0, eb / 10.0))
+        m = torch.randint(0, 2, (e - s, k), generator=gen, device=device, dtype=torch.float32)
+        c = (m @ Gt).to(torch.int64) & 1
+        noise = torch.randn((e - s, n), generator=gen, device=device, dtype=torch.float32)
+        y = (2.0 * c.to(torch.float32) - 1.0) + torch.sqrt(s2)[:, None] * noise
+        llr[s:e] = 2.0 * y / s2[:, None]
+        cws[s:e] = c.to(torch.uint8)
+        snr[s:e] = eb
+    return llr, cws, snr
