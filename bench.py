@@ -40,6 +40,11 @@ WORKLOADS = {
                         "budget 1e5, plain ORBGRAND"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
+    "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),
+                    ebn0=[3.0, 3.5, 4.0, 4.5, 5.0], blocks=10 ** 6, budget=10 ** 6, epochs=2, batch=8192, lr=2e-3,
+                    desc="RLC(128,105) H=[P|I23]: BF16 MLP 128-256-256-64 trained on 1e7 decoder-generated pairs "
+                         "at Eb/N0 ~ U[3,5] dB, reorders the first 64 pattern batches; plain vs learned ORBGRAND "
+                         "on 1e6 held-out blocks per point at 3..5 dB, budget 1e6"),
     "mixed": dict(codes=["rlc64_52", "rlc128_116", "rlc256_240"], ratio=[1, 2, 1],
                   ebn0=[3.0, 3.5, 4.0, 4.5, 5.0, 5.5, 6.0], blocks=4 * 10 ** 6, budget=10 ** 6, tune_point=4.5,
                   desc="RLC (64,52):(128,116):(256,240) = 1:2:1 in one launch, BPSK/AWGN Eb/N0 3..6 dB "
@@ -349,6 +354,91 @@ def run_mixed(args, wl, dev):
     }
 
 
+def run_learned(args, wl, dev):
+    """Train the proposal on decoder-generated pairs, then plain vs learned on
+    held-out blocks (same blocks for both arms)."""
+    import torch
+    from paper_2202_13951_amd import binding, learned
+    from synth import channel, codes
+    H, G = codes.code(wl["code"])
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    xs, ys, seen, i = [], [], 0, 0
+    while sum(int(x.shape[0]) for x in xs) < wl["train_pairs"]:
+        x, y = learned.generate_pairs(H, G, 1 << 21, *wl["train_ebn0"], seed=10 + i, device=dev)
+        xs.append(x)
+        ys.append(y)
+        seen += 1 << 21
+        i += 1
+    x = torch.cat(xs)[: wl["train_pairs"]].contiguous()
+    y = torch.cat(ys)[: wl["train_pairs"]].contiguous()
+    del xs, ys
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    prop = learned.Proposal(dev, seed=0)
+    t0 = time.perf_counter()
+    losses = learned.train(prop, x, y, epochs=wl["epochs"], batch=wl["batch"], lr=wl["lr"],
+                           log=lambda m: print(m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    label_hist = torch.bincount(y.long(), minlength=64)[:8].cpu().tolist()
+    del x, y
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b) / 1e3
+
+    points = {}
+    tot = dict(blocks=0, plain_s=0.0, learned_s=0.0, plain_q=0, learned_q=0)
+    for e in wl["ebn0"]:
+        llr, sent = channel.awgn_llr_torch(G, wl["blocks"], e, seed=5000 + int(round(e * 10)), device=dev)
+        binding.orbg_decode(H, llr[:1024], wl["budget"])                    # warm caches
+        learned.decode_learned(prop, H, llr[:1024], wl["budget"])
+        (pc, pq, pab), pt = timed(lambda: binding.orbg_decode(H, llr, wl["budget"]))
+        (lc, lq, lab), lt = timed(lambda: learned.decode_learned(prop, H, llr, wl["budget"]))
+        pe = (pc != sent).any(dim=1).cpu().numpy()
+        le = (lc != sent).any(dim=1).cpu().numpy()
+        pqn, lqn = pq.cpu().numpy().astype(np.float64), lq.cpu().numpy().astype(np.float64)
+        mu, ci = learned.paired_ci(lqn - pqn)
+        pre = pqn <= learned.PREFIX
+        N = wl["blocks"]
+        points[f"{e:.1f}"] = {
+            "bler_plain": float(pe.mean()), "bler_plain_ci95": list(wilson(int(pe.sum()), N)),
+            "bler_learned": float(le.mean()), "bler_learned_ci95": list(wilson(int(le.sum()), N)),
+            "bler_diff_ci95": list(learned.paired_ci(le.astype(np.float64) - pe.astype(np.float64))[1]),
+            "mean_queries_plain": float(pqn.mean()), "mean_queries_learned": float(lqn.mean()),
+            "queries_diff_mean": mu, "queries_diff_ci95": list(ci),
+            "mean_queries_prefix_blocks_plain": float(pqn[pre].mean()),
+            "mean_queries_prefix_blocks_learned": float(lqn[pre].mean()),
+            "blocks_per_s_plain": N / pt, "blocks_per_s_learned": N / lt,
+            "abandoned_plain": int(pab.sum()), "abandoned_learned": int(lab.sum())}
+        print(f"learned {e} dB: {points[f'{e:.1f}']}", file=sys.stderr, flush=True)
+        tot["blocks"] += N
+        tot["plain_s"] += pt
+        tot["learned_s"] += lt
+        tot["plain_q"] += float(pqn.sum())
+        tot["learned_q"] += float(lqn.sum())
+        del llr, sent, pc, pq, pab, lc, lq, lab
+        torch.cuda.empty_cache()
+    return {
+        "metric": METRIC, "value": tot["blocks"] / tot["learned_s"], "unit": "blocks/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": tot["learned_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 (decode), bf16/fp32 (network)", "data": "synthetic",
+        "config": {"workload": wl["desc"], "code": wl["code"], "ebn0_db": wl["ebn0"],
+                   "blocks_per_point": wl["blocks"], "budget": wl["budget"], "train_pairs": wl["train_pairs"],
+                   "train_ebn0_db": list(wl["train_ebn0"]), "epochs": wl["epochs"], "minibatch": wl["batch"],
+                   "lr": wl["lr"]},
+        "plain_value": tot["blocks"] / tot["plain_s"],
+        "mean_queries_plain": tot["plain_q"] / tot["blocks"], "mean_queries_learned": tot["learned_q"] / tot["blocks"],
+        "pair_generation_s": gen_s, "blocks_decoded_for_pairs": seen, "training_s": train_s,
+        "train_loss_per_epoch": losses, "label_histogram_first8": label_hist, "per_point": points,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,7 +469,12 @@ def main():
         wl["ebn0"] = [e for e in wl["ebn0"] if any(abs(e - x) < 1e-9 for x in args.ebn0)]
         assert wl["ebn0"], "no such Eb/N0 point in the workload"
         wl["desc"] += f" (only Eb/N0 {wl['ebn0']})"
-    result = run_mixed(args, wl, dev) if "codes" in wl else run_single(args, wl, dev)
+    if "codes" in wl:
+        result = run_mixed(args, wl, dev)
+    elif "train_pairs" in wl:
+        result = run_learned(args, wl, dev)
+    else:
+        result = run_single(args, wl, dev)
     if args.ebn0 and "roofline" in result:
         result["roofline"]["traffic"] = None
     print(json.dumps(result), flush=True)

@@ -80,13 +80,21 @@ __device__ __forceinline__ uint2 load_entry(const uint2* __restrict__ sched, uin
 // Mask of the lowest `cnt` lanes.
 __device__ __forceinline__ uint64_t low_lanes(uint32_t cnt) { return cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull); }
 
-// Batch tested at step t: the block's order for the first 64 steps (values
-// taken modulo 64), the plain order afterwards.
+// A block's batch order held in registers: lane l keeps byte l of its row
+// (values taken modulo 64), read once per block.
 template <bool ORDERED>
-__device__ __forceinline__ uint32_t batch_at(const uint8_t* __restrict__ order_row, uint32_t t)
+__device__ __forceinline__ uint32_t load_order(const uint8_t* __restrict__ order_row)
+{
+    return ORDERED ? ((uint32_t)order_row[lane_id()] & 63u) : 0u;
+}
+
+// Batch tested at step t: the block's order for the first 64 steps, the plain
+// order afterwards.
+template <bool ORDERED>
+__device__ __forceinline__ uint32_t batch_at(uint32_t ordv, uint32_t t)
 {
     if (!ORDERED || t >= 64) return t;
-    return uniform_u32(order_row[t]) & 63u;
+    return (uint32_t)__builtin_amdgcn_readlane((int)ordv, (int)t);
 }
 
 template <typename S>
@@ -216,13 +224,16 @@ __device__ __forceinline__ bool light_block(
     const int lane = lane_id();
     const int n = c.n;
     bool ybit[NK];
+    const uint32_t ordv = load_order<ORDERED>(order_row);
     const S s0 = hard_decision<NK, S>(x, n, cols, ybit);
 
     bool found = false;
     uint32_t q = budget;
     uint32_t win_lo = 0, win_hi = 0;     // winning entry (wave-uniform)
 
-    if (!ORDERED && s0 == 0) {
+    // s0 == 0: the empty pattern (entry 0 of batch 0) is a member; it is the first
+    // hit when batch 0 is tested first (always in the plain order)
+    if (s0 == 0 && (!ORDERED || batch_at<ORDERED>(ordv, 0) == 0)) {
         found = true;
         q = 1;
     } else {
@@ -234,7 +245,7 @@ __device__ __forceinline__ bool light_block(
         // query number 64 t + l + 1.  Lanes past the budget or the schedule read a
         // valid entry and are masked out of the ballot.  Indices fit 32 bits.
         uint32_t t = 0;
-        const uint32_t bt = batch_at<ORDERED>(order_row, 0);
+        const uint32_t bt = batch_at<ORDERED>(ordv, 0);
         uint64_t vmA = low_lanes(min(budget, slen - bt * ORBG_WAVE));
         uint2 entA = load_entry(sched, min(bt * ORBG_WAVE + lane, slen - 1));
         uint32_t nhA = scalar_load(bh, bt);
@@ -248,7 +259,7 @@ __device__ __forceinline__ bool light_block(
         auto step = [&](const uint2 cur, const uint32_t nh_cur, const uint64_t vm_cur, uint2& nxt,
                         uint32_t& nh_nxt, uint64_t& vm_nxt) -> int {
             const uint32_t t1 = t + 1;
-            const uint32_t b1 = batch_at<ORDERED>(order_row, t1);
+            const uint32_t b1 = batch_at<ORDERED>(ordv, t1);
             const bool has_next = (t1 * ORBG_WAVE < budget) && (b1 * ORBG_WAVE < slen);
             // loads issued on every path (a valid batch when there is no next
             // step), so the wait for the current entries never covers them

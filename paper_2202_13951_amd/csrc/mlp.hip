@@ -244,6 +244,9 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
 }
 
 // Batch order: decreasing logit, ties (and +-0) to the lower index, NaN last.
+// One wave per row: key = (order-preserving bits of -logit) << 32 | index,
+// sorted ascending by the register bitonic network; lane e then holds the
+// e-th batch to test.
 __global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ logits, int64_t batch,
                                                     uint8_t* __restrict__ order)
 {
@@ -253,13 +256,10 @@ __global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ lo
     const float f = logits[b * MLP_OUT + lane] + 0.0f;          // -0 -> +0
     const uint32_t u = __float_as_uint(f);
     const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
-    const uint32_t key = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f
-    int rank = 0;
-    for (int mm = 0; mm < 64; ++mm) {
-        const uint32_t km = __shfl(key, mm, ORBG_WAVE);
-        rank += (km > key) || (km == key && mm < lane);
-    }
-    order[b * MLP_OUT + rank] = (uint8_t)lane;
+    const uint32_t up = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f, NaN lowest
+    uint64_t key[1] = {((uint64_t)(~up) << 32) | (uint32_t)lane};          // ascending = decreasing f
+    bitonic_sort<1, uint64_t>(key);
+    order[b * MLP_OUT + lane] = (uint8_t)(key[0] & 63u);
 }
 
 // ---------------------------------------------------------------------------
