@@ -24,6 +24,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function",
+    # keep one-lane atomics as written: the work-counter reply is read a chunk later
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

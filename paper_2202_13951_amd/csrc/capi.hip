@@ -37,8 +37,11 @@ struct CodeEntry {
     int dev = 0;
     int n = 0, k = 0;
     std::vector<uint8_t> H;     // host copy, for exact cache matching
-    uint64_t* d_cols = nullptr;
+    uint64_t* d_cols = nullptr; // n columns: bit r of column i = H[r][i]
+    uint64_t* d_rows = nullptr; // (n - k) x nk words: bit l of word j of row r = H[r][64 j + l]
 };
+
+int keys_per_lane(int n);
 
 struct Workspace {
     unsigned long long* ctrs = nullptr;
@@ -105,6 +108,22 @@ int get_code(const uint8_t* H, int n, int k, CodeEntry** out)
         (void)hipFree(c->d_cols);
         delete c;
         return fail(ORBG_EHIP, "copy of packed columns failed");
+    }
+    const int nk = keys_per_lane(n);
+    std::vector<uint64_t> rows((size_t)(n - k) * nk, 0ull);
+    for (int r = 0; r < n - k; ++r)
+        for (int i = 0; i < n; ++i)
+            if (H[(size_t)r * n + i]) rows[(size_t)r * nk + i / 64] |= 1ull << (i % 64);
+    if (hipMalloc(&c->d_rows, sizeof(uint64_t) * rows.size()) != hipSuccess) {
+        (void)hipFree(c->d_cols);
+        delete c;
+        return fail(ORBG_ENOMEM, "cannot allocate %zu packed row words", rows.size());
+    }
+    if (hipMemcpy(c->d_rows, rows.data(), sizeof(uint64_t) * rows.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(c->d_cols);
+        (void)hipFree(c->d_rows);
+        delete c;
+        return fail(ORBG_EHIP, "copy of packed rows failed");
     }
     bucket.push_back(c);
     *out = c;
@@ -231,8 +250,9 @@ int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_bas
     d->slen = (uint32_t)s->len;
     d->col_base = col_base;
     d->cols = c->d_cols;
+    d->rows = c->d_rows;
+    d->row_base = 0;
     d->sched = s->entries;
-    d->bh = s->bh;
     return ORBG_OK;
 }
 
@@ -261,6 +281,7 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     std::memset(&a, 0, sizeof(a));
     a.codes.ncodes = 1;
     if ((rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]))) return rc;
+    a.codes.rwords = a.codes.c[0].m * a.codes.c[0].nk;
     if (batch == 0) return ORBG_OK;
     a.p = resolve_params(params, order != nullptr);
     Workspace* w = nullptr;
@@ -363,11 +384,14 @@ int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, c
     orbg::DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.codes.ncodes = ncodes;
-    uint32_t col_base = 0;
+    uint32_t col_base = 0, row_base = 0;
     for (int i = 0; i < ncodes; ++i) {
         if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i]))) return rc;
+        a.codes.c[i].row_base = row_base;
         col_base += (uint32_t)list[i]->n;
+        row_base += (uint32_t)(a.codes.c[i].m * a.codes.c[i].nk);
     }
+    a.codes.rwords = (int)row_base;
     if (col_base > ORBG_MIXED_COLS)
         return fail(ORBG_EINVAL, "the codes of one mixed decode may hold at most %d columns", ORBG_MIXED_COLS);
     if (batch == 0) return ORBG_OK;

@@ -45,11 +45,14 @@ struct BlockLds {
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// (readfirstlane returns a signed int: each half is taken as uint32_t before
+// widening, or the low half would sign-extend into the high one)
 __device__ __forceinline__ int64_t uniform_i64(int64_t v)
 {
     const uint64_t u = (uint64_t)v;
-    return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
-                     __builtin_amdgcn_readfirstlane((uint32_t)u));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 template <int NK>
@@ -60,6 +63,31 @@ __device__ __forceinline__ void load_row(const float* __restrict__ llr_row, int 
         const int i = j * ORBG_WAVE + lane_id();
         x[j] = (i < n) ? llr_row[i] : 0.0f;
     }
+}
+
+// Raw buffer descriptors (gfx9-family word 3: 32-bit data format).  A lane whose
+// byte offset lies past `bytes` reads 0 and its store is dropped by the
+// hardware, so rows of any length are read and written without branching on the
+// lane, which keeps the count of memory operations in flight the same on every
+// path and lets the next row's loads and this block's stores stay in flight.
+#define ORBG_BUF_DW3 0x00020000
+typedef __amdgpu_buffer_rsrc_t buf_t;
+typedef uint32_t u32x2_t __attribute__((vector_size(8)));
+
+__device__ __forceinline__ buf_t make_buf(const void* base, uint32_t bytes)
+{
+    // descriptors live in scalar registers: base and size are wave-uniform
+    const uint64_t ua = (uint64_t)uniform_i64((int64_t)(uintptr_t)base);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)ua, 0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                             ORBG_BUF_DW3);
+}
+
+template <int NK>
+__device__ __forceinline__ void load_row_buf(buf_t r, float (&x)[NK])
+{
+#pragma unroll
+    for (int j = 0; j < NK; ++j)
+        x[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j * ORBG_WAVE + lane_id()) * 4, 0, 0));
 }
 
 // Read-only tables read with wave-uniform indices: through the constant
@@ -82,10 +110,9 @@ __device__ __forceinline__ uint64_t low_lanes(uint32_t cnt) { return cnt >= 64 ?
 
 // A block's batch order held in registers: lane l keeps byte l of its row
 // (values taken modulo 64), read once per block.
-template <bool ORDERED>
-__device__ __forceinline__ uint32_t load_order(const uint8_t* __restrict__ order_row)
+__device__ __forceinline__ uint32_t load_order_buf(buf_t r)
 {
-    return ORDERED ? ((uint32_t)order_row[lane_id()] & 63u) : 0u;
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, lane_id(), 0, 0) & 63u;
 }
 
 // Batch tested at step t: the block's order for the first 64 steps, the plain
@@ -109,123 +136,205 @@ __device__ __forceinline__ uint32_t wave_xor_reduce_s<uint32_t>(uint32_t v)
 template <>
 __device__ __forceinline__ uint64_t wave_xor_reduce_s<uint64_t>(uint64_t v) { return wave_xor_reduce(v); }
 
-// Steps 1-2: hard decision bits and base syndrome (wave-uniform).
+// Rows of H for this lane: lane r < m holds row r as NK words (bit l of word j
+// = H[r][64 j + l]), other lanes hold zeros.
+template <int NK>
+__device__ __forceinline__ void load_hrows(const uint64_t* rows, int m, uint64_t (&h)[NK])
+{
+    const int r = lane_id() < m ? lane_id() : 0;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const uint64_t w = rows[r * NK + j];
+        h[j] = lane_id() < m ? w : 0ull;
+    }
+}
+
+// Steps 1-2: hard decision bits and base syndrome s0 = H y (wave-uniform).  The
+// ballots of y_i = [LLR_i > 0] are the received word as 64-bit words; bit r of
+// s0 is the parity of (row r of H) AND y, one row per lane.
 template <int NK, typename S>
-__device__ __forceinline__ S hard_decision(const float (&x)[NK], int n, const S* __restrict__ cols, bool (&ybit)[NK])
+__device__ __forceinline__ S hard_decision(const float (&x)[NK], int n, const uint64_t (&hrow)[NK],
+                                           bool (&ybit)[NK])
 {
     const int lane = lane_id();
-    S acc = 0;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        ybit[j] = (j * ORBG_WAVE + lane < n) && (x[j] > 0.0f);
+        const uint64_t y = ballot(ybit[j]);
+        acc += __popc((uint32_t)hrow[j] & (uint32_t)y) + __popc((uint32_t)(hrow[j] >> 32) & (uint32_t)(y >> 32));
+    }
+    return (S)ballot((acc & 1u) != 0u);
+}
+
+template <int NK>
+struct IndexBits { static constexpr int value = NK == 1 ? 6 : NK == 2 ? 7 : NK == 4 ? 8 : NK == 8 ? 9 : 10; };
+
+// Step 3a: received index of every rank, idx[j] for rank lane * NK + j + 1.
+// The sort runs on 32-bit keys (top bits of |LLR| above the index); that order
+// is the order of the full keys (bits of |LLR|) << 32 | index except inside runs
+// of equal truncated magnitudes, so if two neighbours among the ranks the
+// schedule reaches share a truncated magnitude, the full 64-bit keys are
+// sorted instead.  Positions past n hold keys above every element.
+template <int NK>
+__device__ __forceinline__ void rank_order(const float (&x)[NK], int n, int rdepth, uint32_t (&idx)[NK])
+{
+    constexpr int IB = IndexBits<NK>::value;
+    const int lane = lane_id();
+    uint32_t key[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
         const int i = j * ORBG_WAVE + lane;
-        ybit[j] = (i < n) && (x[j] > 0.0f);
-        acc ^= ybit[j] ? cols[i] : (S)0;
+        const uint32_t mag = (i < n) ? (__float_as_uint(x[j]) & 0x7fffffffu) : 0x7fffffffu;
+        key[j] = ((mag >> (IB - 1)) << IB) | (uint32_t)i;
     }
-    return wave_xor_reduce_s<S>(acc);
+    bitonic_sort32<NK>(key);
+    const uint32_t next0 = (uint32_t)__shfl_down((int)key[0], 1, ORBG_WAVE);
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const int e = lane * NK + j;
+        const uint32_t other = (j + 1 < NK) ? key[(j + 1) % NK] : next0;
+        const bool has_next = (j + 1 < NK) || lane + 1 < ORBG_WAVE;
+        tie |= has_next && e < rdepth && ((key[j] ^ other) >> IB) == 0u;
+    }
+    if (ballot(tie) != 0ull) {
+        uint64_t k64[NK];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+            const int i = j * ORBG_WAVE + lane;
+            k64[j] = (i < n) ? (((uint64_t)(__float_as_uint(x[j]) & 0x7fffffffu) << 32) | (uint32_t)i) : ~0ull;
+        }
+        bitonic_sort<NK>(k64);
+#pragma unroll
+        for (int j = 0; j < NK; ++j) idx[j] = (uint32_t)k64[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < NK; ++j) idx[j] = key[j] & ((1u << IB) - 1u);
+    }
 }
 
-// Step 3: reliability order and the per-block lookup tables.
+template <typename S>
+__device__ __forceinline__ S readlane_s(S v, int l);
+template <>
+__device__ __forceinline__ uint32_t readlane_s<uint32_t>(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+template <>
+__device__ __forceinline__ uint64_t readlane_s<uint64_t>(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Step 3: reliability order and the per-block lookup tables: h[r] = column of
+// rank r and pi[r] = its received index for the ranks the schedule reaches,
+// T[m] = s0 XOR (XOR of h_r over the bits r - 1 of m) for the 256 subsets of
+// ranks 1..8 (h_1..h_8 taken from the lanes that hold them).
 template <int NK, typename S>
 __device__ __forceinline__ void rank_and_tables(const float (&x)[NK], int n, const S* __restrict__ cols, S s0,
                                                 int rdepth, BlockLds<S>& L)
 {
     const int lane = lane_id();
-    uint64_t key[NK];
-#pragma unroll
-    for (int j = 0; j < NK; ++j) {
-        const int i = j * ORBG_WAVE + lane;
-        key[j] = (i < n) ? (((uint64_t)(__float_as_uint(x[j]) & 0x7fffffffu) << 32) | (uint32_t)i) : ~0ull;
-    }
-    bitonic_sort<NK>(key);
-    wave_lds_sync();
-    if (lane == 0) { L.h[0] = 0; L.pi[0] = 0; }
+    uint32_t idx[NK];
+    rank_order<NK>(x, n, rdepth, idx);
+    S hv[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
         const int e = lane * NK + j;          // rank e + 1
+        const S col = cols[e < rdepth ? idx[j] : 0u];
+        hv[j] = e < rdepth ? col : (S)0;
         if (e < rdepth) {
-            const uint32_t idx = (uint32_t)key[j];
-            L.h[e + 1] = cols[idx];
-            L.pi[e + 1] = (uint16_t)idx;
-        } else if (e < ORBG_LOW_RANKS) {
-            L.h[e + 1] = 0;                   // ranks beyond n (tiny codes)
+            L.h[e + 1] = hv[j];
+            L.pi[e + 1] = (uint16_t)idx[j];
         }
     }
-    wave_lds_sync();
+    if (lane == 0) { L.h[0] = 0; L.pi[0] = 0; }
+    S hs[ORBG_LOW_RANKS];
+#pragma unroll
+    for (int e = 0; e < ORBG_LOW_RANKS; ++e) hs[e] = readlane_s<S>(hv[e % NK], e / NK);
     S a = s0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? L.h[b + 1] : (S)0;
-    const S h7 = L.h[7], h8 = L.h[8];
+    for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? hs[b] : (S)0;
     L.T[lane] = a;
-    L.T[lane + 64] = a ^ h7;
-    L.T[lane + 128] = a ^ h8;
-    L.T[lane + 192] = a ^ h7 ^ h8;
+    L.T[lane + 64] = a ^ hs[6];
+    L.T[lane + 128] = a ^ hs[7];
+    L.T[lane + 192] = a ^ hs[6] ^ hs[7];
     wave_lds_sync();
 }
 
-// Step 4, one step: syndrome of every lane's entry (all LDS reads before the XORs).
+// Step 4, one step: syndrome of every lane's entry.  Slots past the entry's
+// ranks hold rank 0, whose column is zero; ballots over the wave decide how many
+// slots are read (none when no lane's entry has ranks above 8, three when no
+// lane's entry has more than three).
 template <typename S>
-__device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent, uint32_t nh)
+__device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
 {
-    const S v0 = L.T[ent.x & 0xffu];
-    S v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0;
-    if (nh >= 1) v1 = L.h[(ent.x >> 8) & 0xffu];
-    if (nh >= 2) v2 = L.h[(ent.x >> 16) & 0xffu];
-    if (nh >= 3) v3 = L.h[ent.x >> 24];
-    if (nh >= 4) v4 = L.h[ent.y & 0xffu];
-    if (nh >= 5) v5 = L.h[(ent.y >> 8) & 0xffu];
-    if (nh >= 6) v6 = L.h[(ent.y >> 16) & 0xffu];
-    if (nh >= 7) v7 = L.h[ent.y >> 24];
-    return v0 ^ v1 ^ v2 ^ v3 ^ v4 ^ v5 ^ v6 ^ v7;
+    S v = L.T[ent.x & 0xffu];
+    if (ballot((ent.x >> 8) != 0u) != 0ull) {
+        v ^= L.h[(ent.x >> 8) & 0xffu] ^ L.h[(ent.x >> 16) & 0xffu] ^ L.h[ent.x >> 24];
+        if (ballot(ent.y != 0u) != 0ull)
+            v ^= L.h[ent.y & 0xffu] ^ L.h[(ent.y >> 8) & 0xffu] ^ L.h[(ent.y >> 16) & 0xffu] ^ L.h[ent.y >> 24];
+    }
+    return v;
 }
 
-// Step 5: the hard decision with the winning entry's ranks flipped.
+// Step 5: the hard decision with the winning entry's ranks flipped, stored
+// through the row's buffer descriptor (lanes past n store nothing).
 template <int NK, typename S>
-__device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], int n, const BlockLds<S>& L,
-                                               uint32_t win_lo, uint32_t win_hi, uint8_t* __restrict__ cw_row)
+__device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const BlockLds<S>& L, uint32_t win_lo,
+                                               uint32_t win_hi, buf_t cw_row)
 {
     const int lane = lane_id();
-    if ((win_lo | win_hi) == 0) {
+    bool bit[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) bit[j] = ybit[j];
+    if ((win_lo | win_hi) != 0) {
+        int flip_pos[ORBG_LOW_RANKS + ORBG_HIGH_SLOTS];
+#pragma unroll
+        for (int u = 0; u < ORBG_LOW_RANKS; ++u)
+            flip_pos[u] = ((win_lo >> u) & 1u) ? (int)L.pi[u + 1] : -1;
+#pragma unroll
+        for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
+            const uint32_t r = (u < 4) ? ((win_lo >> (8 * u)) & 0xffu) : ((win_hi >> (8 * (u - 4))) & 0xffu);
+            flip_pos[ORBG_LOW_RANKS + u - 1] = r ? (int)L.pi[r] : -1;
+        }
 #pragma unroll
         for (int j = 0; j < NK; ++j) {
             const int i = j * ORBG_WAVE + lane;
-            if (i < n) cw_row[i] = ybit[j] ? 1 : 0;
-        }
-        return;
-    }
-    int flip_pos[ORBG_LOW_RANKS + ORBG_HIGH_SLOTS];
 #pragma unroll
-    for (int u = 0; u < ORBG_LOW_RANKS; ++u)
-        flip_pos[u] = ((win_lo >> u) & 1u) ? (int)L.pi[u + 1] : -1;
-#pragma unroll
-    for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
-        const uint32_t r = (u < 4) ? ((win_lo >> (8 * u)) & 0xffu) : ((win_hi >> (8 * (u - 4))) & 0xffu);
-        flip_pos[ORBG_LOW_RANKS + u - 1] = r ? (int)L.pi[r] : -1;
-    }
-#pragma unroll
-    for (int j = 0; j < NK; ++j) {
-        const int i = j * ORBG_WAVE + lane;
-        if (i < n) {
-            bool b = ybit[j];
-#pragma unroll
-            for (int u = 0; u < ORBG_LOW_RANKS + ORBG_HIGH_SLOTS; ++u) b ^= (flip_pos[u] == i);
-            cw_row[i] = b ? 1 : 0;
+            for (int u = 0; u < ORBG_LOW_RANKS + ORBG_HIGH_SLOTS; ++u) bit[j] ^= (flip_pos[u] == i);
         }
     }
+#pragma unroll
+    for (int j = 0; j < NK; ++j)
+        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, j * ORBG_WAVE + lane, 0, 0);
+}
+
+// Query count and abandon flag of one block: lane 0's stores are the only ones
+// inside the 8-byte and 1-byte descriptors.
+__device__ __forceinline__ void write_result(uint64_t* q_out, uint8_t* ab_out, uint32_t q, bool abandon)
+{
+    const int lane = lane_id();
+    const u32x2_t v = {q, 0u};
+    __builtin_amdgcn_raw_buffer_store_b64(v, make_buf(q_out, 8), lane * 8, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(abandon ? 1 : 0), make_buf(ab_out, 1), lane, 0, 0);
 }
 
 // Light pass, one block.  Returns true if the block is left for the heavy pass
 // (then nothing is written).
 template <int NK, bool ORDERED, typename S>
 __device__ __forceinline__ bool light_block(
-    const float (&x)[NK], const CodeDesc& c, const S* __restrict__ cols, BlockLds<S>& L,
-    uint32_t budget, uint32_t split_steps, const uint8_t* __restrict__ order_row,
-    uint8_t* __restrict__ cw_row, uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
+    const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
+    BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
+    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
 {
     const int lane = lane_id();
     const int n = c.n;
     bool ybit[NK];
-    const uint32_t ordv = load_order<ORDERED>(order_row);
-    const S s0 = hard_decision<NK, S>(x, n, cols, ybit);
+    const S s0 = hard_decision<NK, S>(x, n, hrow, ybit);
 
     bool found = false;
     uint32_t q = budget;
@@ -239,36 +348,31 @@ __device__ __forceinline__ bool light_block(
     } else {
         rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
         const uint2* __restrict__ sched = c.sched;
-        const uint32_t* __restrict__ bh = c.bh;
         const uint32_t slen = c.slen;
         // Step t tests batch bt; lane l takes schedule entry 64 bt + l, which is
-        // query number 64 t + l + 1.  Lanes past the budget or the schedule read a
-        // valid entry and are masked out of the ballot.  Indices fit 32 bits.
+        // query number 64 t + l + 1.  The queries that exist are the first
+        // lim = min(budget, schedule length), so there are T steps and only the
+        // last one masks lanes.  Indices fit 32 bits.
+        const uint32_t lim = min(budget, slen);
+        const uint32_t T = (lim + ORBG_WAVE - 1) / ORBG_WAVE;
+        const uint64_t tail = low_lanes(lim - (T - 1) * ORBG_WAVE);
         uint32_t t = 0;
-        const uint32_t bt = batch_at<ORDERED>(ordv, 0);
-        uint64_t vmA = low_lanes(min(budget, slen - bt * ORBG_WAVE));
-        uint2 entA = load_entry(sched, min(bt * ORBG_WAVE + lane, slen - 1));
-        uint32_t nhA = scalar_load(bh, bt);
+        uint2 entA = load_entry(sched, min(batch_at<ORDERED>(ordv, 0) * ORBG_WAVE + lane, slen - 1));
         uint2 entB = make_uint2(0u, 0u);
-        uint32_t nhB = 0;
-        uint64_t vmB = 0;
         // One step: load the next step's entries, test the current ones.
         // Returns 0 (go on), 1 (hit), 2 (no hit, nothing left), 3 (split point).
         // The loop alternates two register sets, so a load is consumed one full
         // step after it was issued.
-        auto step = [&](const uint2 cur, const uint32_t nh_cur, const uint64_t vm_cur, uint2& nxt,
-                        uint32_t& nh_nxt, uint64_t& vm_nxt) -> int {
+        auto step = [&](const uint2 cur, uint2& nxt) -> int {
             const uint32_t t1 = t + 1;
-            const uint32_t b1 = batch_at<ORDERED>(ordv, t1);
-            const bool has_next = (t1 * ORBG_WAVE < budget) && (b1 * ORBG_WAVE < slen);
-            // loads issued on every path (a valid batch when there is no next
-            // step), so the wait for the current entries never covers them
-            const uint32_t bl = has_next ? b1 : 0u;
+            const bool has_next = t1 < T;
+            // loads issued on every path (the current batch again when there is
+            // no next step), so the wait for the current entries never covers them
+            const uint32_t bl = batch_at<ORDERED>(ordv, has_next ? t1 : t);
             nxt = load_entry(sched, min(bl * ORBG_WAVE + lane, slen - 1));
-            nh_nxt = scalar_load(bh, bl);
-            vm_nxt = has_next ? low_lanes(min(budget - t1 * ORBG_WAVE, slen - b1 * ORBG_WAVE)) : 0ull;
-            const S syn = entry_syndrome<S>(L, cur, nh_cur);
-            const uint64_t hits = ballot(syn == 0) & vm_cur;
+            const S syn = entry_syndrome<S>(L, cur);
+            uint64_t hits = ballot(syn == 0);
+            if (!has_next) hits &= tail;
             if (hits) {
                 const int wl = __builtin_ctzll(hits);
                 q = t * ORBG_WAVE + wl + 1;
@@ -283,9 +387,13 @@ __device__ __forceinline__ bool light_block(
         };
         int r;
         for (;;) {
-            if ((r = step(entA, nhA, vmA, entB, nhB, vmB)) != 0) break;
-            if ((r = step(entB, nhB, vmB, entA, nhA, vmA)) != 0) break;
+            if ((r = step(entA, entB)) != 0) break;
+            if ((r = step(entB, entA)) != 0) break;
         }
+        // the entries prefetched for a step that will not run are taken here, so
+        // their registers are free when the next block's code reuses them (no
+        // wait on the next block's row at the top of the block loop)
+        asm volatile("" ::"v"(entA.x), "v"(entA.y), "v"(entB.x), "v"(entB.y));
         if (r == 3) {
             wave_lds_sync();
             return true;
@@ -293,34 +401,60 @@ __device__ __forceinline__ bool light_block(
         found = (r == 1);
     }
 
-    write_codeword<NK, S>(ybit, n, L, win_lo, win_hi, cw_row);
-    if (lane == 0) {
-        *q_out = found ? q : budget;
-        *ab_out = found ? 0 : 1;
-    }
+    write_codeword<NK, S>(ybit, L, win_lo, win_hi, cw_row);
+    write_result(q_out, ab_out, found ? q : budget, !found);
     wave_lds_sync();
     return false;
 }
 
 template <int NK, bool ORDERED, typename S>
-__device__ __forceinline__ void light_one(const float (&x)[NK], const CodeDesc& c, const S* cols, BlockLds<S>& L,
-                                          int64_t b, int64_t row, uint32_t budget, uint32_t split_steps,
-                                          const uint8_t* order, uint8_t* cw, uint64_t* queries,
+__device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (&hrow)[NK], uint32_t ordv,
+                                          const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
+                                          uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
                                           uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy)
 {
-    const bool left = light_block<NK, ORDERED, S>(x, c, cols, L, budget, split_steps,
-                                                  ORDERED ? order + b * 64 : nullptr, cw + row, queries + b,
-                                                  abandoned + b);
+    const bool left = light_block<NK, ORDERED, S>(x, hrow, c, cols, L, budget, split_steps, ordv,
+                                                  make_buf(cw + row, (uint32_t)c.n), queries + b, abandoned + b);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
         heavy[slot] = b;
     }
 }
 
+// Next block's inputs, fetched while the current block is decoded.
+template <int NKMAX>
+struct RowFetch {
+    float x[NKMAX];
+    uint32_t ordv;     // batch order (ordered decode)
+    int ci;            // code index (wave-uniform)
+    int64_t row;       // element offset of the row (wave-uniform)
+};
+
+// Byte `i` of a read-only array, by a scalar load of its dword.
+__device__ __forceinline__ uint32_t scalar_load_u8(const uint8_t* p, int64_t i)
+{
+    const uintptr_t a = (uintptr_t)(p + i);
+    return (scalar_load((const uint32_t*)(a & ~(uintptr_t)3), 0) >> ((a & 3) * 8)) & 0xffu;
+}
+
+__device__ __forceinline__ int64_t scalar_load_i64(const int64_t* p, int64_t i)
+{
+    const uint32_t* w = (const uint32_t*)(p + i);
+    return (int64_t)(((uint64_t)scalar_load(w, 1) << 32) | scalar_load(w, 0));
+}
+
 // Light pass.  One wave per workgroup, so the wave's LDS tables sit at fixed
 // addresses.  MIXED: each block names its code (block_code) and row offset;
 // otherwise all blocks use code 0 with rows b * n.  NKMAX: largest keys per
 // lane among the launch's codes.
+//
+// Each wave walks a sequence of blocks: chunks of `chunk` consecutive blocks
+// taken from XCD slice counters (workgroups are dealt round-robin to the 8
+// XCDs, so workgroup w works first on slice w % 8 through that slice's counter,
+// then helps the other slices).  The counter increment for the next chunk is
+// issued when a chunk starts, and the next block's row is loaded while the
+// current block is decoded; the two fetch buffers alternate, so no register
+// copy waits for a load.
 template <int NKMAX, bool ORDERED, typename S, bool MIXED>
 __global__ void __launch_bounds__(ORBG_WAVE)
 light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
@@ -329,72 +463,114 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
              int chunk)
 {
-    // columns of the launch's codes: sum of n entries (dynamic LDS, sized at launch)
+    // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
+    // m x nk words), then their columns (sum of n entries)
     extern __shared__ __align__(16) unsigned char orbg_dyn_lds[];
-    S* s_cols = reinterpret_cast<S*>(orbg_dyn_lds);
+    uint64_t* s_rows = reinterpret_cast<uint64_t*>(orbg_dyn_lds);
+    S* s_cols = reinterpret_cast<S*>(orbg_dyn_lds + (size_t)codes.rwords * sizeof(uint64_t));
     __shared__ BlockLds<S> L;
-    for (int ci = 0; ci < (MIXED ? codes.ncodes : 1); ++ci)
-        for (int i = threadIdx.x; i < codes.c[ci].n; i += ORBG_WAVE)
-            s_cols[codes.c[ci].col_base + i] = (S)codes.c[ci].cols[i];
+    for (int ci = 0; ci < (MIXED ? codes.ncodes : 1); ++ci) {
+        const CodeDesc& c = codes.c[ci];
+        for (int i = threadIdx.x; i < c.n; i += ORBG_WAVE) s_cols[c.col_base + i] = (S)c.cols[i];
+        for (int i = threadIdx.x; i < c.m * c.nk; i += ORBG_WAVE) s_rows[c.row_base + i] = c.rows[i];
+    }
     wave_lds_sync();
     const int lane = lane_id();
+    // one code with at most 4 words per row: the rows stay in registers
+    constexpr bool HOIST = !MIXED && NKMAX <= 4;
+    uint64_t hrow0[NKMAX];
+    if (HOIST) load_hrows<NKMAX>(s_rows, codes.c[0].m, hrow0);
 
-    // XCD-aware work split: workgroups are dealt round-robin to the 8 XCDs, so
-    // workgroup w works first on slice w % 8 of the blocks through that slice's
-    // counter (an atomic in the XCD's own L2), then helps the other slices.
+    // work cursor (wave-uniform): k-th slice visited, its range [lo, hi), end of
+    // the current chunk; `pend` (lane 0) receives the next chunk's counter value
     const int home = (int)(blockIdx.x % ORBG_XCDS);
-    for (int k = 0; k < ORBG_XCDS; ++k) {
-        const int xs = (home + k) % ORBG_XCDS;
-        const int64_t lo = nblocks * xs / ORBG_XCDS, hi = nblocks * (xs + 1) / ORBG_XCDS;
-        unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(xs);
-        unsigned long long c0 = 0;
-        if (lane == 0) c0 = atomicAdd(ctr, (unsigned long long)chunk);
-        int64_t b0 = lo + (int64_t)__shfl(c0, 0, ORBG_WAVE);
-        while (b0 < hi) {
-            unsigned long long c1 = 0;
-            if (lane == 0) c1 = atomicAdd(ctr, (unsigned long long)chunk);   // in flight meanwhile
-            const int64_t end = (b0 + chunk < hi) ? b0 + chunk : hi;
-            if (!MIXED) {
-                constexpr int NK = NKMAX;
-                const CodeDesc& c = codes.c[0];
-                float x[NK];
-                load_row<NK>(llr + b0 * c.n, c.n, x);
-                for (int64_t b = b0; b < end; ++b) {
-                    float xn[NK];
-                    if (b + 1 < end) load_row<NK>(llr + (b + 1) * c.n, c.n, xn);   // next row in flight
-                    light_one<NK, ORDERED, S>(x, c, s_cols, L, b, b * c.n, budget, split_steps, order, cw,
-                                              queries, abandoned, ctrs, heavy);
-#pragma unroll
-                    for (int j = 0; j < NK; ++j) x[j] = xn[j];
-                }
+    int k = 0;
+    int64_t lo = nblocks * home / ORBG_XCDS, hi = nblocks * (home + 1) / ORBG_XCDS, end = 0;
+    unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(home);
+    unsigned long long pend = 0;
+    if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
+    // (every cursor value goes through readfirstlane so that it stays in scalar
+    // registers and the branches on it stay scalar)
+    auto next_block = [&](int64_t b) -> int64_t {
+        if (b + 1 < end) return b + 1;
+        int64_t s;
+        for (;;) {
+            s = uniform_i64(lo + (int64_t)uniform_u64(pend));
+            const bool hit = s < hi;
+            if (hit) {
+                end = uniform_i64((s + chunk < hi) ? s + chunk : hi);
             } else {
-                for (int64_t b = b0; b < end; ++b) {
-                    int ci = (int)uniform_u32(block_code[b]);
-                    ci = ci < codes.ncodes ? ci : 0;      // out-of-range indices read code 0
-                    const CodeDesc& c = codes.c[ci];
-                    const int64_t row = uniform_i64(row_off[b]);
-                    const S* cols = s_cols + c.col_base;
-                    if (c.nk == 1 || NKMAX == 1) {
-                        float x[1];
-                        load_row<1>(llr + row, c.n, x);
-                        light_one<1, ORDERED, S>(x, c, cols, L, b, row, budget, split_steps, order, cw, queries,
-                                                 abandoned, ctrs, heavy);
-                    } else if (c.nk == 2 || NKMAX == 2) {
-                        constexpr int K2 = NKMAX >= 2 ? 2 : 1;
-                        float x[K2];
-                        load_row<K2>(llr + row, c.n, x);
-                        light_one<K2, ORDERED, S>(x, c, cols, L, b, row, budget, split_steps, order, cw, queries,
-                                                  abandoned, ctrs, heavy);
-                    } else {
-                        float x[NKMAX];
-                        load_row<NKMAX>(llr + row, c.n, x);
-                        light_one<NKMAX, ORDERED, S>(x, c, cols, L, b, row, budget, split_steps, order, cw,
-                                                     queries, abandoned, ctrs, heavy);
-                    }
-                }
+                k = (int)uniform_u32((uint32_t)k + 1u);
+                if (k == ORBG_XCDS) return -1;
+                const int xs = (home + k) % ORBG_XCDS;
+                lo = uniform_i64(nblocks * xs / ORBG_XCDS);
+                hi = uniform_i64(nblocks * (xs + 1) / ORBG_XCDS);
+                ctr = ctrs + ORBG_CTR_SLICE(xs);
             }
-            b0 = lo + (int64_t)__shfl(c1, 0, ORBG_WAVE);
+            // one lane increments; the loop leaves only after this branch has joined
+            if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
+            if (hit) break;
         }
+        return s;
+    };
+    // issue the loads of block b's inputs (b < 0: an empty row, every lane reads 0)
+    auto fetch = [&](RowFetch<NKMAX>& f, int64_t b) {
+        int ci = 0;
+        int64_t row = 0;
+        if (b >= 0) {
+            if (MIXED) {
+                ci = (int)scalar_load_u8(block_code, b);
+                ci = ci < codes.ncodes ? ci : 0;          // out-of-range indices read code 0
+                row = scalar_load_i64(row_off, b);
+            } else {
+                row = b * codes.c[0].n;
+            }
+        }
+        f.ci = ci;
+        f.row = row;
+        const uint32_t bytes = b >= 0 ? (uint32_t)codes.c[ci].n * 4u : 0u;
+        load_row_buf<NKMAX>(make_buf(llr + row, bytes), f.x);
+        f.ordv = ORDERED ? load_order_buf(make_buf(order + (b >= 0 ? b : 0) * 64, b >= 0 ? 64u : 0u)) : 0u;
+    };
+    auto decode = [&](const RowFetch<NKMAX>& f, int64_t b) {
+        const CodeDesc& c = codes.c[MIXED ? f.ci : 0];
+        const S* cols = s_cols + (MIXED ? c.col_base : 0);
+        if (HOIST) {
+            light_one<NKMAX, ORDERED, S>(f.x, hrow0, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw,
+                                         queries, abandoned, ctrs, heavy);
+        } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
+            uint64_t hr[NKMAX];
+            load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);
+            light_one<NKMAX, ORDERED, S>(f.x, hr, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw, queries,
+                                         abandoned, ctrs, heavy);
+        } else if (c.nk == 1) {
+            uint64_t hr[1];
+            load_hrows<1>(s_rows + c.row_base, c.m, hr);
+            light_one<1, ORDERED, S>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, b, f.row,
+                                     budget, split_steps, cw, queries, abandoned, ctrs, heavy);
+        } else {
+            constexpr int K2 = NKMAX >= 2 ? 2 : 1;
+            uint64_t hr[K2];
+            load_hrows<K2>(s_rows + c.row_base, c.m, hr);
+            light_one<K2, ORDERED, S>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L, b,
+                                      f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy);
+        }
+    };
+
+    int64_t b = uniform_i64(next_block(-1));
+    if (b < 0) return;
+    RowFetch<NKMAX> fa, fb;
+    fetch(fa, b);
+    auto advance = [&](const RowFetch<NKMAX>& cur, RowFetch<NKMAX>& nxt) -> bool {
+        const int64_t bn = uniform_i64(next_block(b));
+        fetch(nxt, bn);
+        decode(cur, b);
+        b = bn;
+        return bn >= 0;
+    };
+    for (;;) {
+        if (!advance(fa, fb)) break;
+        if (!advance(fb, fa)) break;
     }
 }
 
@@ -416,7 +592,9 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
     bool ybit[NK];
     if (wave == 0) {
         load_row<NK>(llr_row, n, x);
-        const S s0 = hard_decision<NK, S>(x, n, s_cols, ybit);
+        uint64_t hr[NK];
+        load_hrows<NK>(c.rows, c.m, hr);
+        const S s0 = hard_decision<NK, S>(x, n, hr, ybit);
         rank_and_tables<NK, S>(x, n, s_cols, s0, c.rdepth, L);
     }
     __syncthreads();
@@ -425,22 +603,20 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
     // wave w takes steps split + w, split + w + G, ...; the next one's entries
     // are loaded while the current one is tested
     uint32_t t = split_steps + wave;
-    if (t * ORBG_WAVE < budget && t * ORBG_WAVE < slen) {
+    const uint32_t lim = min(budget, slen);
+    if (t * ORBG_WAVE < lim) {
         uint2 entA = load_entry(sched, min(t * ORBG_WAVE + lane, slen - 1));
-        uint32_t nhA = scalar_load(c.bh, t);
         uint2 entB = make_uint2(0u, 0u);
-        uint32_t nhB = 0;
         // returns true when this wave is done (hit, nothing left, or an earlier hit known)
-        auto step = [&](const uint2 cur, const uint32_t nh_cur, uint2& nxt, uint32_t& nh_nxt) -> bool {
+        auto step = [&](const uint2 cur, uint2& nxt) -> bool {
             if (t * ORBG_WAVE + 1 > __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
                 return true;
             const uint32_t t1 = t + G;
-            const bool has_next = t1 * ORBG_WAVE < budget && t1 * ORBG_WAVE < slen;
+            const bool has_next = t1 * ORBG_WAVE < lim;
             const uint32_t tl = has_next ? t1 : t;            // loads on every path
             nxt = load_entry(sched, min(tl * ORBG_WAVE + lane, slen - 1));
-            nh_nxt = scalar_load(c.bh, tl);
-            const uint64_t vmask = low_lanes(min(budget - t * ORBG_WAVE, slen - t * ORBG_WAVE));
-            const S syn = entry_syndrome<S>(L, cur, nh_cur);
+            const uint64_t vmask = low_lanes(lim - t * ORBG_WAVE);
+            const S syn = entry_syndrome<S>(L, cur);
             const uint64_t hits = ballot(syn == 0) & vmask;
             if (hits) {
                 if (lane == 0) atomicMin(best, t * ORBG_WAVE + (uint32_t)__builtin_ctzll(hits) + 1);
@@ -451,8 +627,8 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
             return false;
         };
         for (;;) {
-            if (step(entA, nhA, entB, nhB)) break;
-            if (step(entB, nhB, entA, nhA)) break;
+            if (step(entA, entB)) break;
+            if (step(entB, entA)) break;
         }
     }
     __syncthreads();
@@ -465,11 +641,8 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
             win_lo = uniform_u32(w.x);
             win_hi = uniform_u32(w.y);
         }
-        write_codeword<NK, S>(ybit, n, L, win_lo, win_hi, cw_row);
-        if (lane == 0) {
-            *q_out = found ? q : budget;
-            *ab_out = found ? 0 : 1;
-        }
+        write_codeword<NK, S>(ybit, L, win_lo, win_hi, make_buf(cw_row, (uint32_t)n));
+        write_result(q_out, ab_out, found ? q : budget, !found);
     }
     __syncthreads();
 }
@@ -530,7 +703,8 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
         const uint32_t e = a.codes.c[i].col_base + (uint32_t)a.codes.c[i].n;
         ncols = e > ncols ? e : ncols;
     }
-    light_kernel<NKMAX, ORDERED, S, MIXED><<<(unsigned)wgs, ORBG_WAVE, ncols * sizeof(S), stream>>>(
+    const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
+    light_kernel<NKMAX, ORDERED, S, MIXED><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
         a.abandoned, a.ctrs, a.heavy, chunk);
 }

@@ -92,4 +92,72 @@ __device__ __forceinline__ void bitonic_sort(KEY (&key)[NK])
     }
 }
 
+// Value of lane (lane XOR LD) for a wave-constant distance LD, all lanes active:
+// quad permutes for 1 and 2, a half-row mirror composed with a quad reversal for
+// 4 (7 - (i ^ 3) = i ^ 4 inside each group of 8), a half-row rotation for 8, an
+// LDS-crossbar swizzle (xor mask 16 inside 32 lanes) for 16 and a bpermute for 32.
+template <int LD>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
+{
+    static_assert(LD == 1 || LD == 2 || LD == 4 || LD == 8 || LD == 16 || LD == 32, "lane distance");
+    if constexpr (LD == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    } else if constexpr (LD == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    } else if constexpr (LD == 4) {
+        const int m = __builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);     // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, false);        // quad_perm [3,2,1,0]
+    } else if constexpr (LD == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (LD == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);               // and 0x1f, xor 0x10
+    } else {
+        return (uint32_t)__shfl_xor((int)v, 32, 64);
+    }
+}
+
+// Ascending bitonic sort of 64*NK distinct u32 keys, element e = lane * NK + j
+// in register j of its lane (same network as bitonic_sort), with the lane
+// exchanges of lane_xor: no LDS traffic below lane distance 16.
+template <int NK>
+__device__ __forceinline__ void bitonic_sort32(uint32_t (&key)[NK])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= ORBG_WAVE * NK; size <<= 1) {
+#pragma unroll
+        for (int d = size >> 1; d > 0; d >>= 1) {
+            if (d < NK) {
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    if ((j & d) == 0) {
+                        const bool desc = ((lane * NK + j) & size) != 0;
+                        const uint32_t a = key[j], b = key[j | d];
+                        const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                        key[j] = desc ? hi : lo;
+                        key[j | d] = desc ? lo : hi;
+                    }
+                }
+            } else {
+                const int ld = d / NK;
+                const bool keep_min = ((lane & ld) == 0) == (((lane * NK) & size) == 0);
+#pragma unroll
+                for (int j = 0; j < NK; ++j) {
+                    uint32_t p;
+                    switch (ld) {
+                        case 1: p = lane_xor<1>(key[j]); break;
+                        case 2: p = lane_xor<2>(key[j]); break;
+                        case 4: p = lane_xor<4>(key[j]); break;
+                        case 8: p = lane_xor<8>(key[j]); break;
+                        case 16: p = lane_xor<16>(key[j]); break;
+                        default: p = lane_xor<32>(key[j]); break;
+                    }
+                    const uint32_t lo = p < key[j] ? p : key[j], hi = p < key[j] ? key[j] : p;
+                    key[j] = keep_min ? lo : hi;
+                }
+            }
+        }
+    }
+}
+
 }  // namespace orbg

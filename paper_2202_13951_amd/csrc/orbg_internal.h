@@ -31,7 +31,6 @@ struct Schedule {
     uint64_t len;       // number of valid entries
     uint2* entries;     // nbatch * 64 packed entries: byte 0 = mask of ranks 1..8 (bit j = rank j+1),
                         // bytes 1..7 = ranks above 8, ascending, 0 = none
-    uint32_t* bh;       // per batch of 64: largest number of ranks above 8 in an entry
     uint64_t nbatch;
     int rmax;           // largest rank any entry references
     int wlast;          // logistic weight of the last entry

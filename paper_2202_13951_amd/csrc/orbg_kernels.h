@@ -16,14 +16,15 @@ struct CodeDesc {
     int rdepth;                // ranks whose columns are staged (<= 255)
     uint32_t slen;             // schedule entries
     uint32_t col_base;         // first column of this code in the launch's LDS column table
+    uint32_t row_base;         // first word of this code's rows in the launch's LDS row table
     const uint64_t* cols;      // n packed parity-check columns
+    const uint64_t* rows;      // m x nk packed parity-check rows (bit l of word j = H[r][64 j + l])
     const uint2* sched;        // schedule entries for this n
-    const uint32_t* bh;        // per-batch count of ranks above 8
 };
 
 struct CodeTable {
     int ncodes;
-    int pad;
+    int rwords;                // row words of all codes (LDS row table size)
     CodeDesc c[ORBG_MAX_CODES];
 };
 

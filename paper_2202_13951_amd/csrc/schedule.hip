@@ -133,28 +133,25 @@ __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes,
     }
 }
 
-__global__ void batch_width_kernel(const uint2* entries, uint64_t len, uint32_t* bh, uint64_t nbatch,
-                                   int* rmax)
+// Deepest rank referenced by the first `len` entries (one thread per batch of 64).
+__global__ void rank_depth_kernel(const uint2* entries, uint64_t len, uint64_t nbatch, int* rmax)
 {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbatch) return;
-    int hmax = 0, r = 0;
+    int r = 0;
     for (uint64_t g = b * 64; g < b * 64 + 64 && g < len; ++g) {
         const uint2 e2 = entries[g];
         const uint64_t e = ((uint64_t)e2.y << 32) | e2.x;
-        int h = 0;
         for (int i = 1; i <= ORBG_HIGH_SLOTS; ++i) {
             const int rk = (int)((e >> (8 * i)) & 0xff);
-            if (rk) { h = i; r = rk > r ? rk : r; }
+            r = rk > r ? rk : r;
         }
         const int low = (int)(e & 0xff);
         if (low) {
             const int top = 32 - __clz(low);          // highest set bit + 1 = rank
             r = top > r ? top : r;
         }
-        hmax = h > hmax ? h : hmax;
     }
-    bh[b] = (uint32_t)hmax;
     atomicMax(rmax, r);
 }
 
@@ -206,23 +203,20 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     }
     const uint64_t nbatch = (len + 63) / 64;
     uint2* d_entries = nullptr;
-    uint32_t* d_bw = nullptr;
-    if (hipMalloc(&d_entries, sizeof(uint2) * nbatch * 64) != hipSuccess ||
-        hipMalloc(&d_bw, sizeof(uint32_t) * nbatch) != hipSuccess) {
+    if (hipMalloc(&d_entries, sizeof(uint2) * nbatch * 64) != hipSuccess) {
         snprintf(err, errlen, "schedule: cannot allocate %llu entries", (unsigned long long)len);
-        (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
+        (void)hipFree(d_classes); (void)hipFree(d_small);
         return -2;
     }
     // entries past len (up to the batch boundary) stay zero: the empty pattern
     (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * nbatch * 64, stream);
     class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, len, d_classes, nclass, d_entries);
-    batch_width_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, d_bw, nbatch,
-                                                                            d_small + 2);
+    rank_depth_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, nbatch, d_small + 2);
     int rmax = 0;
     (void)hipMemcpyAsync(&rmax, d_small + 2, sizeof(int), hipMemcpyDeviceToHost, stream);
     if (hipStreamSynchronize(stream) != hipSuccess) {
         snprintf(err, errlen, "schedule: fill kernels failed: %s", hipGetErrorString(hipGetLastError()));
-        (void)hipFree(d_entries); (void)hipFree(d_bw); (void)hipFree(d_classes); (void)hipFree(d_small);
+        (void)hipFree(d_entries); (void)hipFree(d_classes); (void)hipFree(d_small);
         return -3;
     }
     (void)hipFree(d_classes);
@@ -230,7 +224,6 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     out->n = n;
     out->len = len;
     out->entries = d_entries;
-    out->bh = d_bw;
     out->nbatch = nbatch;
     out->rmax = rmax;
     out->wlast = host_small[1];
