@@ -58,8 +58,8 @@ extern "C" {
  */
 typedef struct orbg_launch_params {
     int workgroups_per_cu;        /* light pass, 1..64 (default 32) */
-    int chunk;                    /* blocks taken per work-counter increment, 1..4096 (default: about
-                                     16 increments per wave) */
+    int chunk;                    /* blocks taken per work-counter increment, 1..64 (default: about
+                                     4 increments per wave, at most 64) */
     int split_steps;              /* -1 = default (64), 0 = no heavy pass, else steps before the split;
                                      an ordered decode moves values below 64 up to 64 */
     int heavy_waves;              /* 4, 8 or 16 (default 8) */

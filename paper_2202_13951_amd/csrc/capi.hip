@@ -220,7 +220,7 @@ int check_params(const orbg_launch_params* p)
     if (!p) return ORBG_OK;
     if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 64)
         return fail(ORBG_EINVAL, "workgroups_per_cu = %d outside [0, 64]", p->workgroups_per_cu);
-    if (p->chunk < 0 || p->chunk > 4096) return fail(ORBG_EINVAL, "chunk = %d outside [0, 4096]", p->chunk);
+    if (p->chunk < 0 || p->chunk > 64) return fail(ORBG_EINVAL, "chunk = %d outside [0, 64]", p->chunk);
     if (p->split_steps < -1) return fail(ORBG_EINVAL, "split_steps = %d below -1", p->split_steps);
     if (p->heavy_waves != 0 && p->heavy_waves != 4 && p->heavy_waves != 8 && p->heavy_waves != 16)
         return fail(ORBG_EINVAL, "heavy_waves = %d is not 0, 4, 8 or 16", p->heavy_waves);

@@ -282,7 +282,9 @@ __device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
 }
 
 // Step 5: the hard decision with the winning entry's ranks flipped, stored
-// through the row's buffer descriptor (lanes past n store nothing).
+// through the row's buffer descriptor (lanes past n store nothing).  The
+// received position of each flipped rank is wave-uniform; the lane holding it
+// toggles its bit.
 template <int NK, typename S>
 __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const BlockLds<S>& L, uint32_t win_lo,
                                                uint32_t win_hi, buf_t cw_row)
@@ -291,22 +293,17 @@ __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const Blo
     bool bit[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) bit[j] = ybit[j];
-    if ((win_lo | win_hi) != 0) {
-        int flip_pos[ORBG_LOW_RANKS + ORBG_HIGH_SLOTS];
+    auto flip = [&](uint32_t r) {
+        const uint32_t p = uniform_u32(L.pi[r]);
 #pragma unroll
-        for (int u = 0; u < ORBG_LOW_RANKS; ++u)
-            flip_pos[u] = ((win_lo >> u) & 1u) ? (int)L.pi[u + 1] : -1;
+        for (int j = 0; j < NK; ++j)
+            if ((p >> 6) == (uint32_t)j) bit[j] ^= (uint32_t)lane == (p & 63u);
+    };
+    for (uint32_t low = win_lo & 0xffu; low != 0; low &= low - 1) flip((uint32_t)__builtin_ctz(low) + 1u);
 #pragma unroll
-        for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
-            const uint32_t r = (u < 4) ? ((win_lo >> (8 * u)) & 0xffu) : ((win_hi >> (8 * (u - 4))) & 0xffu);
-            flip_pos[ORBG_LOW_RANKS + u - 1] = r ? (int)L.pi[r] : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < NK; ++j) {
-            const int i = j * ORBG_WAVE + lane;
-#pragma unroll
-            for (int u = 0; u < ORBG_LOW_RANKS + ORBG_HIGH_SLOTS; ++u) bit[j] ^= (flip_pos[u] == i);
-        }
+    for (int u = 1; u <= ORBG_HIGH_SLOTS; ++u) {
+        const uint32_t r = (u < 4) ? ((win_lo >> (8 * u)) & 0xffu) : ((win_hi >> (8 * (u - 4))) & 0xffu);
+        if (r != 0) flip(r);
     }
 #pragma unroll
     for (int j = 0; j < NK; ++j)
@@ -346,7 +343,6 @@ __device__ __forceinline__ bool light_block(
         found = true;
         q = 1;
     } else {
-        rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
         const uint2* __restrict__ sched = c.sched;
         const uint32_t slen = c.slen;
         // Step t tests batch bt; lane l takes schedule entry 64 bt + l, which is
@@ -356,23 +352,28 @@ __device__ __forceinline__ bool light_block(
         const uint32_t lim = min(budget, slen);
         const uint32_t T = (lim + ORBG_WAVE - 1) / ORBG_WAVE;
         const uint64_t tail = low_lanes(lim - (T - 1) * ORBG_WAVE);
+        // entries of step u (the last step's again past the end, so that every
+        // path issues the same loads)
+        // (a schedule holds whole batches of 64 entries, so no lane reads past it)
+        auto entries = [&](uint32_t u) -> uint2 {
+            const uint32_t bu = batch_at<ORDERED>(ordv, u < T ? u : T - 1);
+            return load_entry(sched + (size_t)bu * ORBG_WAVE, (uint32_t)lane);
+        };
+        // the first three steps' entries do not depend on the block's order of
+        // reliability: they load while the ranks are sorted
+        uint2 e0 = entries(0), e1 = entries(1), e2 = entries(2), e3 = make_uint2(0u, 0u);
+        rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
         uint32_t t = 0;
-        uint2 entA = load_entry(sched, min(batch_at<ORDERED>(ordv, 0) * ORBG_WAVE + lane, slen - 1));
-        uint2 entB = make_uint2(0u, 0u);
-        // One step: load the next step's entries, test the current ones.
+        // One step: load the entries of step t + 3, test those of step t.
         // Returns 0 (go on), 1 (hit), 2 (no hit, nothing left), 3 (split point).
-        // The loop alternates two register sets, so a load is consumed one full
-        // step after it was issued.
-        auto step = [&](const uint2 cur, uint2& nxt) -> int {
-            const uint32_t t1 = t + 1;
-            const bool has_next = t1 < T;
-            // loads issued on every path (the current batch again when there is
-            // no next step), so the wait for the current entries never covers them
-            const uint32_t bl = batch_at<ORDERED>(ordv, has_next ? t1 : t);
-            nxt = load_entry(sched, min(bl * ORBG_WAVE + lane, slen - 1));
+        // Four register sets rotate, so a load is consumed three steps after it
+        // was issued.
+        auto step = [&](const uint2 cur, uint2& ahead) -> int {
+            ahead = entries(t + 3);
             const S syn = entry_syndrome<S>(L, cur);
             uint64_t hits = ballot(syn == 0);
-            if (!has_next) hits &= tail;
+            const bool last = t + 1 >= T;
+            if (last) hits &= tail;
             if (hits) {
                 const int wl = __builtin_ctzll(hits);
                 q = t * ORBG_WAVE + wl + 1;
@@ -380,20 +381,23 @@ __device__ __forceinline__ bool light_block(
                 win_hi = __builtin_amdgcn_readlane(cur.y, wl);
                 return 1;
             }
-            if (!has_next) return 2;
-            if (split_steps != 0 && t1 >= split_steps) return 3;
-            t = t1;
+            if (last) return 2;
+            ++t;
+            if (split_steps != 0 && t >= split_steps) return 3;
             return 0;
         };
         int r;
         for (;;) {
-            if ((r = step(entA, entB)) != 0) break;
-            if ((r = step(entB, entA)) != 0) break;
+            if ((r = step(e0, e3)) != 0) break;
+            if ((r = step(e1, e0)) != 0) break;
+            if ((r = step(e2, e1)) != 0) break;
+            if ((r = step(e3, e2)) != 0) break;
         }
-        // the entries prefetched for a step that will not run are taken here, so
+        // the entries prefetched for steps that will not run are taken here, so
         // their registers are free when the next block's code reuses them (no
         // wait on the next block's row at the top of the block loop)
-        asm volatile("" ::"v"(entA.x), "v"(entA.y), "v"(entB.x), "v"(entB.y));
+        asm volatile("" ::"v"(e0.x), "v"(e0.y), "v"(e1.x), "v"(e1.y), "v"(e2.x), "v"(e2.y), "v"(e3.x),
+                     "v"(e3.y));
         if (r == 3) {
             wave_lds_sync();
             return true;
@@ -443,18 +447,38 @@ __device__ __forceinline__ int64_t scalar_load_i64(const int64_t* p, int64_t i)
     return (int64_t)(((uint64_t)scalar_load(w, 1) << 32) | scalar_load(w, 0));
 }
 
+// Rows of H for this lane padded to NK words (words past the code's nk are zero).
+template <int NK>
+__device__ __forceinline__ void load_hrows_pad(const uint64_t* rows, int m, int nk, uint64_t (&h)[NK])
+{
+    const int r = lane_id() < m ? lane_id() : 0;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const uint64_t w = j < nk ? rows[r * nk + j] : 0ull;
+        h[j] = lane_id() < m ? w : 0ull;
+    }
+}
+
+// Rows in flight per screening group: 16 row registers per lane.
+template <int NKMAX>
+struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; };
+
 // Light pass.  One wave per workgroup, so the wave's LDS tables sit at fixed
 // addresses.  MIXED: each block names its code (block_code) and row offset;
 // otherwise all blocks use code 0 with rows b * n.  NKMAX: largest keys per
 // lane among the launch's codes.
 //
-// Each wave walks a sequence of blocks: chunks of `chunk` consecutive blocks
-// taken from XCD slice counters (workgroups are dealt round-robin to the 8
-// XCDs, so workgroup w works first on slice w % 8 through that slice's counter,
-// then helps the other slices).  The counter increment for the next chunk is
-// issued when a chunk starts, and the next block's row is loaded while the
-// current block is decoded; the two fetch buffers alternate, so no register
-// copy waits for a load.
+// Each wave takes chunks of `chunk` (at most 64) consecutive blocks from XCD
+// slice counters (workgroups are dealt round-robin to the 8 XCDs, so workgroup
+// w works first on slice w % 8 through that slice's counter, then helps the
+// other slices); the counter increment for the next chunk is issued when a
+// chunk starts.  A chunk is decoded in two phases:
+//   1. screening: the rows are read K at a time, all K loads in flight
+//      together, and every block whose base syndrome is zero (query 1 is a
+//      member and comes first) is written out at once;
+//   2. the other blocks (a 64-bit mask) are decoded one by one, the next one's
+//      row loaded while the current one is decoded; the two fetch buffers
+//      alternate, so no register copy waits for a load.
 template <int NKMAX, bool ORDERED, typename S, bool MIXED>
 __global__ void __launch_bounds__(ORBG_WAVE)
 light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
@@ -489,10 +513,10 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(home);
     unsigned long long pend = 0;
     if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
-    // (every cursor value goes through readfirstlane so that it stays in scalar
-    // registers and the branches on it stay scalar)
-    auto next_block = [&](int64_t b) -> int64_t {
-        if (b + 1 < end) return b + 1;
+    // start of the next chunk (its end in `end`), or -1 when every slice is
+    // drained.  Every cursor value goes through readfirstlane so that it stays
+    // in scalar registers and the branches on it stay scalar.
+    auto next_chunk = [&]() -> int64_t {
         int64_t s;
         for (;;) {
             s = uniform_i64(lo + (int64_t)uniform_u64(pend));
@@ -513,19 +537,77 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
         return s;
     };
-    // issue the loads of block b's inputs (b < 0: an empty row, every lane reads 0)
+    // code index and row offset of block b (wave-uniform)
+    auto locate = [&](int64_t b, int& ci, int64_t& row) {
+        if (MIXED) {
+            ci = (int)scalar_load_u8(block_code, b);
+            ci = ci < codes.ncodes ? ci : 0;          // out-of-range indices read code 0
+            row = scalar_load_i64(row_off, b);
+        } else {
+            ci = 0;
+            row = b * codes.c[0].n;
+        }
+    };
+
+    // phase 1 over [s, e): returns the mask (bit b - s) of the blocks left
+    constexpr int K = ScreenDepth<NKMAX>::value;
+    auto screen = [&](int64_t s, int64_t e) -> uint64_t {
+        uint64_t left = 0;
+        for (int64_t g = s; g < e; g += K) {
+            float xs[K][NKMAX];
+            int cis[K];
+            int64_t rows[K];
+            uint32_t first[K];
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const bool ok = g + kk < e;
+                int ci = 0;
+                int64_t row = 0;
+                if (ok) locate(g + kk, ci, row);
+                cis[kk] = ci;
+                rows[kk] = row;
+                load_row_buf<NKMAX>(make_buf(llr + row, ok ? (uint32_t)codes.c[ci].n * 4u : 0u), xs[kk]);
+                // ordered decode: the block's first batch (every lane reads byte 0)
+                first[kk] = ORDERED ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(
+                                          make_buf(order + (ok ? g + kk : 0) * 64, ok ? 1u : 0u), 0, 0, 0)
+                                    : 0u;
+            }
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const int64_t b = g + kk;
+                if (b < e) {
+                    const CodeDesc& c = codes.c[cis[kk]];
+                    uint64_t hr[NKMAX];
+                    if (HOIST) {
+#pragma unroll
+                        for (int j = 0; j < NKMAX; ++j) hr[j] = hrow0[j];
+                    } else {
+                        load_hrows_pad<NKMAX>(s_rows + c.row_base, c.m, c.nk, hr);
+                    }
+                    bool yb[NKMAX];
+                    const S s0 = hard_decision<NKMAX, S>(xs[kk], c.n, hr, yb);
+                    const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u);
+                    if (done) {
+                        const buf_t cwr = make_buf(cw + rows[kk], (uint32_t)c.n);
+#pragma unroll
+                        for (int j = 0; j < NKMAX; ++j)
+                            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, j * ORBG_WAVE + lane,
+                                                                 0, 0);
+                        write_result(queries + b, abandoned + b, 1u, false);
+                    } else {
+                        left |= 1ull << (b - s);
+                    }
+                }
+            }
+        }
+        return left;
+    };
+
+    // phase 2: the inputs of block b (b < 0: an empty row, every lane reads 0)
     auto fetch = [&](RowFetch<NKMAX>& f, int64_t b) {
         int ci = 0;
         int64_t row = 0;
-        if (b >= 0) {
-            if (MIXED) {
-                ci = (int)scalar_load_u8(block_code, b);
-                ci = ci < codes.ncodes ? ci : 0;          // out-of-range indices read code 0
-                row = scalar_load_i64(row_off, b);
-            } else {
-                row = b * codes.c[0].n;
-            }
-        }
+        if (b >= 0) locate(b, ci, row);
         f.ci = ci;
         f.row = row;
         const uint32_t bytes = b >= 0 ? (uint32_t)codes.c[ci].n * 4u : 0u;
@@ -557,20 +639,25 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
     };
 
-    int64_t b = uniform_i64(next_block(-1));
-    if (b < 0) return;
-    RowFetch<NKMAX> fa, fb;
-    fetch(fa, b);
-    auto advance = [&](const RowFetch<NKMAX>& cur, RowFetch<NKMAX>& nxt) -> bool {
-        const int64_t bn = uniform_i64(next_block(b));
-        fetch(nxt, bn);
-        decode(cur, b);
-        b = bn;
-        return bn >= 0;
-    };
-    for (;;) {
-        if (!advance(fa, fb)) break;
-        if (!advance(fb, fa)) break;
+    for (int64_t s = uniform_i64(next_chunk()); s >= 0; s = uniform_i64(next_chunk())) {
+        uint64_t left = screen(s, end);
+        if (left == 0) continue;
+        int64_t b = s + __builtin_ctzll(left);
+        left &= left - 1;
+        RowFetch<NKMAX> fa, fb;
+        fetch(fa, b);
+        auto advance = [&](const RowFetch<NKMAX>& cur, RowFetch<NKMAX>& nxt) -> bool {
+            const int64_t bn = left ? s + __builtin_ctzll(left) : -1;
+            left &= left - 1;
+            fetch(nxt, bn);
+            decode(cur, b);
+            b = bn;
+            return bn >= 0;
+        };
+        for (;;) {
+            if (!advance(fa, fb)) break;
+            if (!advance(fb, fa)) break;
+        }
     }
 }
 
@@ -725,9 +812,12 @@ static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
     if (wgs > cap) wgs = cap;
     int chunk = a.p.chunk;
     if (chunk <= 0) {
-        const int64_t c = a.nblocks / (wgs * 16);       // about 16 chunks per wave
+        // about 4 chunks per wave: a counter increment is a round trip to L2,
+        // so chunks stay as long as the balance at the end allows
+        const int64_t c = a.nblocks / (wgs * 4);
         chunk = (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
     }
+    chunk = chunk > 64 ? 64 : chunk;                    // a chunk's blocks fit one 64-bit mask
     const uint32_t split = (a.heavy != nullptr && a.p.split_steps > 0) ? (uint32_t)a.p.split_steps : 0u;
     reset_counters_kernel<<<1, 64, 0, stream>>>(a.ctrs);
     launch_light<NKMAX, ORDERED, S, MIXED>(a, wgs, chunk, split, stream);

@@ -116,48 +116,89 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
     }
 }
 
+// Lane masks of the bitonic network (compile-time constants): in a cross-lane
+// substep of stage `size` at lane distance ld, the lanes that keep the smaller
+// key; in an in-lane substep, the lanes whose register j runs descending.
+constexpr uint64_t keep_min_mask(int nk, int size, int ld)
+{
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (((l & ld) == 0) == (((l * nk) & size) == 0)) m |= 1ull << l;
+    return m;
+}
+constexpr uint64_t desc_mask(int nk, int size, int j)
+{
+    uint64_t m = 0;
+    for (int l = 0; l < 64; ++l)
+        if (((l * nk + j) & size) != 0) m |= 1ull << l;
+    return m;
+}
+
+// Per-lane bit of a constant lane mask.  The two scalar moves are written out
+// so that the constant is made where it is used: the compiler would otherwise
+// hoist it out of the block loop, spill it and reload it with vector
+// instructions.
+template <uint64_t M>
+__device__ __forceinline__ bool lane_bit()
+{
+    uint32_t lo, hi;
+    asm volatile("s_mov_b32 %0, %2\n\ts_mov_b32 %1, %3"
+                 : "=s"(lo), "=s"(hi)
+                 : "i"((int32_t)(uint32_t)M), "i"((int32_t)(uint32_t)(M >> 32)));
+    return __builtin_amdgcn_inverse_ballot_w64(((uint64_t)hi << 32) | lo);
+}
+
+// One in-lane compare-exchange of registers J and J | D (for every J without bit D).
+template <int NK, int SIZE, int D, int J>
+__device__ __forceinline__ void bitonic_inlane32(uint32_t (&key)[NK])
+{
+    if constexpr (J < NK) {
+        if constexpr ((J & D) == 0) {
+            const bool desc = lane_bit<desc_mask(NK, SIZE, J)>();
+            const uint32_t a = key[J], b = key[J | D];
+            const bool sw = (a > b) != desc;
+            key[J] = sw ? b : a;
+            key[J | D] = sw ? a : b;
+        }
+        bitonic_inlane32<NK, SIZE, D, J + 1>(key);
+    }
+}
+
+// Substeps D, D/2, ..., 1 of stage SIZE.
+template <int NK, int SIZE, int D>
+__device__ __forceinline__ void bitonic_step32(uint32_t (&key)[NK])
+{
+    if constexpr (D >= NK) {
+        constexpr int LD = D / NK;
+        const bool keep_min = lane_bit<keep_min_mask(NK, SIZE, LD)>();
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+            const uint32_t p = lane_xor<LD>(key[j]);
+            const bool take_p = (p < key[j]) == keep_min;
+            key[j] = take_p ? p : key[j];
+        }
+    } else {
+        bitonic_inlane32<NK, SIZE, D, 0>(key);
+    }
+    if constexpr (D > 1) bitonic_step32<NK, SIZE, D / 2>(key);
+}
+
+template <int NK, int SIZE>
+__device__ __forceinline__ void bitonic_stage32(uint32_t (&key)[NK])
+{
+    bitonic_step32<NK, SIZE, SIZE / 2>(key);
+    if constexpr (SIZE < ORBG_WAVE * NK) bitonic_stage32<NK, SIZE * 2>(key);
+}
+
 // Ascending bitonic sort of 64*NK distinct u32 keys, element e = lane * NK + j
 // in register j of its lane (same network as bitonic_sort), with the lane
-// exchanges of lane_xor: no LDS traffic below lane distance 16.
+// exchanges of lane_xor (no LDS traffic below lane distance 16) and the stage
+// directions as constant scalar lane masks: a compare-exchange is a lane
+// exchange, one compare and one select.
 template <int NK>
 __device__ __forceinline__ void bitonic_sort32(uint32_t (&key)[NK])
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int size = 2; size <= ORBG_WAVE * NK; size <<= 1) {
-#pragma unroll
-        for (int d = size >> 1; d > 0; d >>= 1) {
-            if (d < NK) {
-#pragma unroll
-                for (int j = 0; j < NK; ++j) {
-                    if ((j & d) == 0) {
-                        const bool desc = ((lane * NK + j) & size) != 0;
-                        const uint32_t a = key[j], b = key[j | d];
-                        const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                        key[j] = desc ? hi : lo;
-                        key[j | d] = desc ? lo : hi;
-                    }
-                }
-            } else {
-                const int ld = d / NK;
-                const bool keep_min = ((lane & ld) == 0) == (((lane * NK) & size) == 0);
-#pragma unroll
-                for (int j = 0; j < NK; ++j) {
-                    uint32_t p;
-                    switch (ld) {
-                        case 1: p = lane_xor<1>(key[j]); break;
-                        case 2: p = lane_xor<2>(key[j]); break;
-                        case 4: p = lane_xor<4>(key[j]); break;
-                        case 8: p = lane_xor<8>(key[j]); break;
-                        case 16: p = lane_xor<16>(key[j]); break;
-                        default: p = lane_xor<32>(key[j]); break;
-                    }
-                    const uint32_t lo = p < key[j] ? p : key[j], hi = p < key[j] ? key[j] : p;
-                    key[j] = keep_min ? lo : hi;
-                }
-            }
-        }
-    }
+    bitonic_stage32<NK, 2>(key);
 }
 
 }  // namespace orbg

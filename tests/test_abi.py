@@ -45,7 +45,7 @@ def test_ordered_needs_n_at_least_12():
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("workgroups_per_cu", 65, "workgroups_per_cu"), ("chunk", 5000, "chunk"), ("split_steps", -2, "split_steps"),
+    ("workgroups_per_cu", 65, "workgroups_per_cu"), ("chunk", 65, "chunk"), ("split_steps", -2, "split_steps"),
     ("heavy_waves", 5, "heavy_waves"), ("heavy_workgroups_per_cu", 17, "heavy_workgroups_per_cu")])
 def test_launch_params_are_checked(field, value, msg):
     L = binding.load()
