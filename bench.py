@@ -5,16 +5,22 @@ Eb/N0 = 4.0, 4.5, ..., 7.0 dB, 10^6 blocks per point, query budget 10^5, plain
 ORBGRAND.  One step decodes all 7 x 10^6 blocks (LLRs already resident in HBM)
 with one decode call (light pass + heavy pass).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bch127|rlc32|mixed]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bch127|rlc32|mixed|learned|stream]
 
 --workload mixed: random linear codes (64,52), (128,116), (256,240) mixed 1:2:1
 in one persistent launch per Eb/N0 point (3..6 dB, 4x10^6 blocks, budget
 10^6), against the same blocks decoded by one launch per code without the
 heavy pass.
+--workload learned: the learned batch-order proposal on RLC(128,105), trained
+on the GPU, against plain ORBGRAND on the same held-out blocks.
+--workload stream: Poisson request arrivals (single blocks of four codes) served
+by a host loop of mixed-code launches; p50/p99 latency and blocks/s at 1e5 and
+1e6 requests/s.
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -45,6 +51,17 @@ WORKLOADS = {
                     desc="RLC(128,105) H=[P|I23]: BF16 MLP 128-256-256-64 trained on 1e7 decoder-generated pairs "
                          "at Eb/N0 ~ U[3,5] dB, reorders the first 64 pattern batches; plain vs learned ORBGRAND "
                          "on 1e6 held-out blocks per point at 3..5 dB, budget 1e6"),
+    "stream": dict(codes=["rlc64_52", "bch127_113", "rlc128_116", "rlc256_240"], ratio=[1, 1, 1, 1],
+                   ebn0_range=(3.0, 6.0), rates=[1e5, 1e6], seconds=1.0, budget=10 ** 5,
+                   capacity=1 << 16, max_batch=1 << 13, streams=8,
+                   launch=dict(workgroups_per_cu=32, chunk=1, split_steps=16, heavy_waves=16,
+                               heavy_workgroups_per_cu=2),
+                   desc="request stream: Poisson arrivals of single blocks, codes RLC(64,52), BCH(127,113), "
+                        "RLC(128,116), RLC(256,240) uniformly mixed, Eb/N0 ~ U[3,6] dB per request, budget "
+                        "1e5, 1 s of arrivals at 1e5 and 1e6 requests/s; LLRs and outputs resident in HBM; "
+                        "a host loop launches every arrived request (at most 8192 per launch, at most 65536 "
+                        "in flight) as one mixed-code decode, launches dealt round-robin to 8 streams, blocks "
+                        "past 16 steps shared by 16 waves"),
     "mixed": dict(codes=["rlc64_52", "rlc128_116", "rlc256_240"], ratio=[1, 2, 1],
                   ebn0=[3.0, 3.5, 4.0, 4.5, 5.0, 5.5, 6.0], blocks=4 * 10 ** 6, budget=10 ** 6, tune_point=4.5,
                   desc="RLC (64,52):(128,116):(256,240) = 1:2:1 in one launch, BPSK/AWGN Eb/N0 3..6 dB "
@@ -354,6 +371,121 @@ def run_mixed(args, wl, dev):
     }
 
 
+def run_stream(args, wl, dev):
+    """Serving loop over a Poisson request stream.  Arrivals are on the host clock
+    (perf_counter from t0); completions on the GPU clock, as the elapsed time from an
+    event recorded at t0 to the event recorded after each launch.  Latency =
+    completion - arrival.  Every result is compared with one decode of all requests."""
+    import collections
+    import torch
+    from paper_2202_13951_amd import binding
+    from synth import codes, mixed
+    from synth import stream as arrivals
+    HG = [codes.code(nm) for nm in wl["codes"]]
+    ids = [binding.orbg_code_register(H) for H, _ in HG]
+    params, knobs = binding.LaunchParams(**wl["launch"]), wl["launch"]
+    s = torch.cuda.current_stream()
+    # launches go round-robin to several streams of default priority, so one long
+    # block does not hold up the launches behind it
+    streams = [torch.cuda.Stream() for _ in range(wl["streams"])]
+    per_rate = {}
+    for ri, rate in enumerate(wl["rates"]):
+        N = int(round(rate * wl["seconds"]))
+        llr, sent, bc, ro, snr = mixed.mixed_llr_torch_snr_range([G for _, G in HG], wl["ratio"], N,
+                                                                 *wl["ebn0_range"], seed=3000 + ri, device=dev)
+        t_arr = arrivals.poisson_arrivals(N, rate, seed=4000 + ri)
+        cw = torch.zeros_like(sent)
+        q = torch.zeros(N, dtype=torch.int64, device=dev)
+        ab = torch.zeros(N, dtype=torch.uint8, device=dev)
+        # schedules of every code and the work spaces of every stream exist before the clock starts
+        # (work spaces sized for the largest launch, so none grows on the clock)
+        w = min(N, wl["max_batch"])
+        for st in streams:
+            binding.orbg_decode_mixed(ids, bc[:w], ro[:w], llr, wl["budget"], cw, q[:w], ab[:w],
+                                      params=params, stream=st)
+        torch.cuda.synchronize()
+        inflight, batches = [collections.deque() for _ in streams], []
+        n_in, nxt, k = 0, 0, 0
+        gc.collect()
+        gc.disable()                                  # no collector pauses on the clock
+        e0 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s)
+        torch.cuda.synchronize()
+        align = time.perf_counter() - t0              # bound on the host/GPU clock offset
+        while nxt < N or any(inflight):
+            for fl in inflight:
+                while fl and fl[0][0].query():
+                    ev, lo, hi = fl.popleft()
+                    n_in -= hi - lo
+                    batches.append((ev, lo, hi, time.perf_counter() - t0))
+            if nxt < N:
+                j = int(np.searchsorted(t_arr, time.perf_counter() - t0, side="right"))
+                j = min(j, nxt + wl["max_batch"], nxt + wl["capacity"] - n_in)
+                if j > nxt:
+                    st = streams[k]
+                    binding.orbg_decode_mixed(ids, bc[nxt:j], ro[nxt:j], llr, wl["budget"], cw, q[nxt:j],
+                                              ab[nxt:j], params=params, stream=st)
+                    ev = torch.cuda.Event(enable_timing=True)
+                    ev.record(st)
+                    inflight[k].append((ev, nxt, j))
+                    k = (k + 1) % len(streams)
+                    n_in += j - nxt
+                    nxt = j
+        torch.cuda.synchronize()
+        gc.enable()
+        # completion on the GPU clock (a lower bound: the GPU stamps e0 a little
+        # after t0) and as first seen by the host loop (an upper bound)
+        done, seen = np.empty(N), np.empty(N)
+        for ev, lo, hi, th in batches:
+            done[lo:hi] = e0.elapsed_time(ev) / 1e3
+            seen[lo:hi] = th
+        lat = (done - t_arr) * 1e6
+        lat_host = (seen - t_arr) * 1e6
+        sizes = np.array([hi - lo for _, lo, hi, _ in batches])
+        # the same requests as one decode
+        cw1, q1, ab1 = torch.zeros_like(sent), torch.zeros_like(q), torch.zeros_like(ab)
+        binding.orbg_decode_mixed(ids, bc, ro, llr, wl["budget"], cw1, q1, ab1, params=params)
+        torch.cuda.synchronize()
+        same = bool((q == q1).all()) and bool((ab == ab1).all()) and bool((cw == cw1).all())
+        per_code = {}
+        bc_np = bc.cpu().numpy()
+        for ci, (H, _) in enumerate(HG):
+            n = H.shape[1]
+            idx = torch.nonzero(bc == ci).flatten()
+            pos = ro[idx][:, None] + torch.arange(n, device=dev)[None, :]
+            ne = int((cw[pos] != sent[pos]).any(dim=1).sum())
+            nb = int(idx.numel())
+            per_code[wl["codes"][ci]] = {"requests": nb, "bler": ne / max(nb, 1),
+                                         "mean_queries": float(q[idx].double().mean()),
+                                         "p99_latency_us": float(np.percentile(lat[bc_np == ci], 99))}
+        span = float(done.max() - t_arr[0])
+        per_rate[f"{rate:.0e}"] = {
+            "requests": N, "blocks_per_s": N / span, "offered_per_s": rate,
+            "latency_us": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max()),
+                           "mean": float(lat.mean())},
+            "latency_host_us": {"p50": float(np.percentile(lat_host, 50)),
+                                "p99": float(np.percentile(lat_host, 99)), "max": float(lat_host.max())},
+            "launches": len(batches), "mean_launch_blocks": float(sizes.mean()),
+            "max_launch_blocks": int(sizes.max()), "clock_alignment_us": align * 1e6,
+            "queries_per_s": float(q.sum()) / span, "identical_to_one_decode": same, "per_code": per_code}
+        print(f"stream {rate:.0e}/s: p50 {np.percentile(lat, 50):.0f} us p99 {np.percentile(lat, 99):.0f} us, "
+              f"{N / span:.3g} blocks/s, {len(batches)} launches", file=sys.stderr, flush=True)
+        del llr, sent, bc, ro, snr, cw, q, ab, cw1, q1, ab1
+        torch.cuda.empty_cache()
+    top = per_rate[f"{wl['rates'][-1]:.0e}"]
+    return {
+        "metric": METRIC, "value": top["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": 1e3 * wl["seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": wl["desc"], "codes": wl["codes"], "rates_per_s": wl["rates"],
+                   "ebn0_db_range": list(wl["ebn0_range"]), "budget": wl["budget"],
+                   "capacity": wl["capacity"], "max_batch": wl["max_batch"]},
+        "launch_params": knobs if knobs else "library defaults", "per_rate": per_rate,
+    }
+
+
 def run_learned(args, wl, dev):
     """Train the proposal on decoder-generated pairs, then plain vs learned on
     held-out blocks (same blocks for both arms)."""
@@ -469,7 +601,9 @@ def main():
         wl["ebn0"] = [e for e in wl["ebn0"] if any(abs(e - x) < 1e-9 for x in args.ebn0)]
         assert wl["ebn0"], "no such Eb/N0 point in the workload"
         wl["desc"] += f" (only Eb/N0 {wl['ebn0']})"
-    if "codes" in wl:
+    if "rates" in wl:
+        result = run_stream(args, wl, dev)
+    elif "codes" in wl:
         result = run_mixed(args, wl, dev)
     elif "train_pairs" in wl:
         result = run_learned(args, wl, dev)

@@ -64,3 +64,28 @@ def mixed_llr_torch(gens, ratio, n_blocks: int, ebn0_db: float, seed: int, devic
         llr[pos] = x.reshape(-1)
         sent[pos] = c.reshape(-1)
     return llr, sent, bc, ro
+
+
+def mixed_llr_torch_snr_range(gens, ratio, n_blocks: int, ebn0_lo: float, ebn0_hi: float, seed: int, device):
+    """torch on `device`: like mixed_llr_torch, but every block draws its own
+    Eb/N0 uniformly in [lo, hi] dB.  Returns (llr, sent, block_code, row_offset, ebn0)."""
+    import torch
+    ns = [G.shape[1] for G in gens]
+    block_code, row_offset, total = plan(ns, ratio, n_blocks, seed)
+    bc = torch.from_numpy(block_code).to(device)
+    ro = torch.from_numpy(row_offset).to(device)
+    llr = torch.empty(total, dtype=torch.float32, device=device)
+    sent = torch.empty(total, dtype=torch.uint8, device=device)
+    snr = torch.empty(n_blocks, dtype=torch.float32, device=device)
+    for ci, G in enumerate(gens):
+        idx = torch.nonzero(bc == ci).flatten()
+        if idx.numel() == 0:
+            continue
+        x, c, e = channel.awgn_llr_torch_snr_range(G, idx.numel(), ebn0_lo, ebn0_hi, seed=seed * 31 + ci,
+                                                   device=device)
+        n = G.shape[1]
+        pos = (ro[idx][:, None] + torch.arange(n, device=device)[None, :]).reshape(-1)
+        llr[pos] = x.reshape(-1)
+        sent[pos] = c.reshape(-1)
+        snr[idx] = e
+    return llr, sent, bc, ro, snr

@@ -62,3 +62,31 @@ def test_paper_snr_calibration():
     of 1e-3 (Sec. IV-A): Q(sqrt(10^0.98)) is 1e-3 to two digits."""
     p = _Q(math.sqrt(10 ** 0.98))
     assert abs(p - 1e-3) < 0.05e-3
+
+
+def test_poisson_arrivals_rate_and_gaps():
+    """Exponential gaps: mean 1/rate, coefficient of variation 1, P(gap > 1/rate) = 1/e."""
+    from synth import stream
+    t = stream.poisson_arrivals(200000, 1e5, seed=3)
+    assert t[0] == 0.0 and (np.diff(t) >= 0).all()
+    g = np.diff(t)
+    assert abs(g.mean() * 1e5 - 1) < 0.01
+    assert abs(g.std() / g.mean() - 1) < 0.01
+    assert abs((g > 1e-5).mean() - np.exp(-1)) < 0.005
+    assert (stream.poisson_arrivals(1000, 1e6, seed=3) == stream.poisson_arrivals(1000, 1e6, seed=3)).all()
+
+
+def test_mixed_snr_range_layout():
+    """Per-block Eb/N0 in range, rows at their offsets are codewords' noisy images of the right length."""
+    import torch
+    from synth import codes, mixed
+    gens = [codes.code(nm)[1] for nm in ("rlc64_52", "bch127_113")]
+    llr, sent, bc, ro, snr = mixed.mixed_llr_torch_snr_range(gens, [1, 1], 400, 3.0, 6.0, seed=9, device="cpu")
+    assert llr.shape == sent.shape and bc.shape == (400,) and snr.shape == (400,)
+    assert float(snr.min()) >= 3.0 and float(snr.max()) <= 6.0
+    ns = np.array([64, 127])[bc.numpy()]
+    assert (np.diff(ro.numpy()) == ns[:-1]).all() and int(ro[-1]) + ns[-1] == llr.numel()
+    for i in range(0, 400, 37):
+        H, _ = codes.code(("rlc64_52", "bch127_113")[int(bc[i])])
+        c = sent[int(ro[i]):int(ro[i]) + ns[i]].numpy().astype(np.int64)
+        assert not ((H.astype(np.int64) @ c) % 2).any()
