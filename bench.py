@@ -86,6 +86,29 @@ def algorithmic_ops(q_sum: int, n_sorted: int, n: int) -> float:
     return 4.0 * q_sum + 2.0 * n * math.ceil(math.log2(n)) * n_sorted
 
 
+def query_breakdown(q, ab, err, budget, sweep=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 5, 10 ** 6)):
+    """Counts and mean queries of the blocks decoded correctly, decoded to another
+    codeword, and abandoned; and the abandonment sweep: a decode with budget b below
+    the run's returns the same result for blocks with q <= b and abandons the others,
+    so BLER and mean queries at every smaller budget follow from one decode."""
+    q = np.asarray(q, dtype=np.int64)
+    ab = np.asarray(ab) != 0
+    err = np.asarray(err, dtype=bool)
+
+    def stats(m):
+        return {"blocks": int(m.sum()), "mean_queries": float(q[m].mean()) if m.any() else None}
+    out = {"correct": stats(~err & ~ab), "incorrect": stats(err & ~ab), "abandoned": stats(ab)}
+    sw = {}
+    for b in sweep:
+        if b > budget:
+            continue
+        kept = q <= b
+        sw[f"{b:.0e}"] = {"bler": float(((err & kept) | ~kept).mean()), "abandoned": float((~kept).mean()),
+                          "mean_queries": float(np.minimum(q, b).mean())}
+    out["budget_sweep"] = sw
+    return out
+
+
 def kernel_fingerprint() -> str:
     """sha256 (first 16 hex digits) over the names and contents of the kernel sources."""
     import glob
@@ -115,24 +138,28 @@ def profiled_traffic(workload: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(H, llr_host_points, budget, target_s=10.0):
-    """Times the oracle (as it stands) on the first blocks of every Eb/N0 point."""
+def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0):
+    """Times the oracle (as it stands) on the first blocks of every Eb/N0 point.
+    rows(p, count) -> host float32 [count, n], the first `count` rows of point p.
+    A first pass on 2000 blocks per point sizes the sample (that pass overstates the
+    per-block cost, so the timed sample lasts about half of target_s)."""
     from oracle import oracle as O
     threads = len(os.sched_getaffinity(0))
-    per = 200
-    # calibrate the sample so the timed oracle work lasts about target_s seconds
+    per = min(2000, per_max)
+    xs = [rows(p, per) for p in range(npoints)]
     t0 = time.perf_counter()
-    for x in llr_host_points:
-        O.decode(H, x[:per], budget, threads)
+    for x in xs:
+        O.decode(H, x, budget, threads)
     dt = time.perf_counter() - t0
-    per = int(min(len(llr_host_points[0]), max(per, per * target_s / max(dt, 1e-3))))
+    per = int(min(per_max, max(per, per * target_s / max(dt, 1e-3))))
+    xs = [rows(p, per) for p in range(npoints)]
     t0 = time.perf_counter()
-    for x in llr_host_points:
-        O.decode(H, x[:per], budget, threads)
+    for x in xs:
+        O.decode(H, x, budget, threads)
     dt = time.perf_counter() - t0
-    nb = per * len(llr_host_points)
+    nb = per * npoints
     return {"value": nb / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {per} blocks of each of the {len(llr_host_points)} Eb/N0 points "
+            "sample": f"first {per} blocks of each of the {npoints} Eb/N0 points "
                       f"({nb} blocks, {dt:.1f} s wall)"}
 
 
@@ -232,6 +259,7 @@ def run_single(args, wl, dev):
         ne = int(err[sl].sum())
         lo, hi = wilson(ne, B)
         per_point[f"{e:.1f}"] = {"bler": ne / B, "errors": ne, "bler_ci95": [lo, hi],
+                                 "breakdown": query_breakdown(q_np[sl], ab_np[sl], err[sl], budget),
                                  "mean_queries": float(q_np[sl].mean()),
                                  "p99_queries": float(np.percentile(q_np[sl], 99)),
                                  "abandoned": int(ab_np[sl].sum())}
@@ -284,9 +312,7 @@ def run_single(args, wl, dev):
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu_baseline:
-        idx = [np.arange(p * B, p * B + min(B, 50000)) for p in range(P)]
-        host_pts = [llr[torch.from_numpy(i).to(dev)].cpu().numpy() for i in idx]
-        result["cpu_baseline"] = cpu_baseline(H, host_pts, budget)
+        result["cpu_baseline"] = cpu_baseline(H, lambda p, c: llr[p * B:p * B + c].cpu().numpy(), P, B, budget)
     return result
 
 

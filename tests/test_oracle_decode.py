@@ -8,7 +8,9 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from synth import codes
+from synth import channel, codes
+
+THREADS = 4
 
 
 def _abs_bits(x):
@@ -235,3 +237,19 @@ def test_ordered_identity_equals_plain_and_far_hits_unchanged():
     assert (c2[far] == c0[far]).all() and (q2[far] == q0[far]).all() and (a2[far] == a0[far]).all()
     near = ~far
     assert (q2[near] <= 4096).all()
+
+
+def test_budget_truncation_is_exact():
+    """A decode with a smaller budget b returns the full-budget result for blocks with
+    q <= b and abandons the others with q = b and the hard decision (the order of
+    patterns does not depend on the budget).  This is what makes the abandonment sweep
+    of one decode exact."""
+    H, G = codes.code("bch127_113")
+    llr, _ = channel.awgn_llr(G, 300, 4.0, seed=77)
+    cw, q, ab = O.decode(H, llr, 10 ** 4, THREADS)
+    y = (llr > 0).astype(np.uint8)
+    for b in (1, 7, 64, 500, 3000):
+        cb, qb, abb = O.decode(H, llr, b, THREADS)
+        kept = q <= b
+        assert (qb[kept] == q[kept]).all() and (abb[kept] == ab[kept]).all() and (cb[kept] == cw[kept]).all()
+        assert (qb[~kept] == b).all() and (abb[~kept] == 1).all() and (cb[~kept] == y[~kept]).all()
