@@ -11,8 +11,9 @@
  *   - Parity-check matrix H: HOST pointer, (n - k) rows by n columns,
  *     row-major, one byte per entry, each 0 or 1.  1 <= n <= 1024 and
  *     1 <= n - k <= 64.  The library copies and packs it (column i becomes a
- *     64-bit word whose bit r is H[r][i]) into a device cache keyed by its
- *     contents; the caller keeps ownership of H.  If H has rank below n - k the
+ *     64-bit word whose bit r is H[r][i]; row r becomes 64-bit words whose bit
+ *     l of word j is H[r][64 j + l]) into a device cache keyed by its contents;
+ *     the caller keeps ownership of H.  If H has rank below n - k the
  *     decoder decodes the code H defines (k only sizes H).
  *   - LLRs: DEVICE pointer, `batch` rows of n FP32 values, row-major, the log
  *     ratio log f(Y|1)/f(Y|0) of Sec. III-A (positive means bit 1).  Values are
