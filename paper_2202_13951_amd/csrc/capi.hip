@@ -247,6 +247,7 @@ int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_bas
     d->m = c->n - c->k;
     d->nk = keys_per_lane(c->n);
     d->rdepth = s->rmax < c->n ? s->rmax : c->n;
+    d->rdepth0 = s->rmax0 < d->rdepth ? s->rmax0 : d->rdepth;
     d->slen = (uint32_t)s->len;
     d->col_base = col_base;
     d->cols = c->d_cols;

@@ -229,6 +229,111 @@ __device__ __forceinline__ uint64_t readlane_s<uint64_t>(uint64_t v, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Step 3 for the first batch only: the ra (<= 32) least reliable ranks without
+// ranking the whole block.  The threshold t is on the truncated magnitude (the
+// key without its index bits), so keys with equal truncated magnitudes fall on
+// the same side of it; it moves from the caller's guess (kept from block to
+// block) until ra <= #(keys below t) <= 32, at most 8 tries.  The keys below t
+// are gathered into lanes 0..31 through LDS and sorted there; lane l < ra then
+// holds the received index of rank l + 1.  Returns false when no such t is found
+// or when two neighbours among the first ra + 1 gathered keys share a truncated
+// magnitude (their order would need the full keys): the caller then ranks the
+// whole block.
+template <int NK, typename S>
+__device__ __forceinline__ bool rank_first(const float (&x)[NK], int n, int ra, uint32_t& guess, BlockLds<S>& L,
+                                           uint32_t& idx1)
+{
+    constexpr int IB = IndexBits<NK>::value;
+    constexpr uint32_t PMAX = 1u << (32 - IB);          // truncated magnitudes are < PMAX
+    constexpr uint32_t OCT = 1u << (24 - IB);           // one binade in truncated-magnitude units
+    const int lane = lane_id();
+    uint32_t key[NK];
+    bool real[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const int i = j * ORBG_WAVE + lane;
+        real[j] = i < n;
+        const uint32_t mag = real[j] ? (__float_as_uint(x[j]) & 0x7fffffffu) : 0x7fffffffu;
+        key[j] = ((mag >> (IB - 1)) << IB) | (uint32_t)i;
+    }
+    uint32_t t = guess >> (IB - 1), lo = 0, hi = PMAX, cnt = 0;   // guess: IEEE bits of a magnitude
+    bool ok = false;
+    for (int it = 0; it < 8; ++it) {
+        cnt = 0;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) cnt += (uint32_t)__builtin_popcountll(ballot(real[j] && (key[j] >> IB) < t));
+        if (cnt >= (uint32_t)ra && cnt <= 32u) { ok = true; break; }
+        // one binade up or down until the window is bracketed, then bisection
+        if (cnt < (uint32_t)ra) {
+            lo = t;
+            t = (hi == PMAX) ? (t < PMAX - OCT ? t + OCT : PMAX - 1) : lo + (hi - lo) / 2;
+        } else {
+            hi = t;
+            t = (lo == 0) ? (t > OCT ? t - OCT : t / 2) : lo + (hi - lo) / 2;
+        }
+        t = uniform_u32(t);
+    }
+    if (!ok) return false;
+    // gather: keys below t to LDS slots 0..cnt-1 (T is rebuilt afterwards)
+    uint32_t* stage = reinterpret_cast<uint32_t*>(L.T);
+    uint32_t base = 0;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const bool c = real[j] && (key[j] >> IB) < t;
+        const uint64_t m = ballot(c);
+        const uint32_t slot =
+            base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (c) stage[slot] = key[j];
+        base += (uint32_t)__builtin_popcountll(m);
+    }
+    wave_lds_sync();
+    uint32_t k1[1] = {(uint32_t)lane < cnt ? stage[lane] : 0xffffffffu};
+    wave_lds_sync();
+    bitonic_sort32_groups<32>(k1);
+    const uint32_t next = (uint32_t)__shfl_down((int)k1[0], 1, ORBG_WAVE);
+    const bool tie = lane < ra && (uint32_t)lane + 1 < cnt && ((k1[0] ^ next) >> IB) == 0u;
+    if (ballot(tie) != 0ull) return false;
+    idx1 = k1[0] & ((1u << IB) - 1u);
+    // next block's guess: just above the middle of the window
+    const uint32_t mid = cnt > 22u ? 22u : (cnt > 0u ? cnt - 1u : 0u);
+    const uint32_t g = ((uint32_t)__builtin_amdgcn_readlane((int)k1[0], (int)mid) >> IB) + 1u;
+    guess = uniform_u32((g < PMAX ? g : PMAX - 1) << (IB - 1));
+    return true;
+}
+
+// Per-wave state of the first-batch ranking (wave-uniform).
+struct LazyState {
+    uint32_t tau;      // threshold guess: IEEE bits of a magnitude
+    uint32_t score;    // ~256 x recent rate of blocks decided by the first batch
+    uint32_t tries;    // blocks that needed a search
+};
+
+// Tables for the first batch after rank_first: h[r], pi[r] for r <= ra and T.
+template <typename S>
+__device__ __forceinline__ void first_tables(uint32_t idx1, int ra, const S* __restrict__ cols, S s0,
+                                             BlockLds<S>& L)
+{
+    const int lane = lane_id();
+    const S col = cols[lane < ra ? idx1 : 0u];
+    const S hv = lane < ra ? col : (S)0;
+    if (lane < ra) {
+        L.h[lane + 1] = hv;
+        L.pi[lane + 1] = (uint16_t)idx1;
+    }
+    if (lane == 0) { L.h[0] = 0; L.pi[0] = 0; }
+    S hs[ORBG_LOW_RANKS];
+#pragma unroll
+    for (int e = 0; e < ORBG_LOW_RANKS; ++e) hs[e] = readlane_s<S>(hv, e);
+    S a = s0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? hs[b] : (S)0;
+    L.T[lane] = a;
+    L.T[lane + 64] = a ^ hs[6];
+    L.T[lane + 128] = a ^ hs[7];
+    L.T[lane + 192] = a ^ hs[6] ^ hs[7];
+    wave_lds_sync();
+}
+
 // Step 3: reliability order and the per-block lookup tables: h[r] = column of
 // rank r and pi[r] = its received index for the ranks the schedule reaches,
 // T[m] = s0 XOR (XOR of h_r over the bits r - 1 of m) for the 256 subsets of
@@ -266,18 +371,19 @@ __device__ __forceinline__ void rank_and_tables(const float (&x)[NK], int n, con
 }
 
 // Step 4, one step: syndrome of every lane's entry.  Slots past the entry's
-// ranks hold rank 0, whose column is zero; ballots over the wave decide how many
-// slots are read (none when no lane's entry has ranks above 8, three when no
-// lane's entry has more than three).
+// ranks hold rank 0, whose column is zero: the low-rank table and the first
+// three slots are read together (one LDS round trip), the last four only when
+// some lane's entry has more than three ranks above 8 (a ballot).
 template <typename S>
 __device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
 {
-    S v = L.T[ent.x & 0xffu];
-    if (ballot((ent.x >> 8) != 0u) != 0ull) {
-        v ^= L.h[(ent.x >> 8) & 0xffu] ^ L.h[(ent.x >> 16) & 0xffu] ^ L.h[ent.x >> 24];
-        if (ballot(ent.y != 0u) != 0ull)
-            v ^= L.h[ent.y & 0xffu] ^ L.h[(ent.y >> 8) & 0xffu] ^ L.h[(ent.y >> 16) & 0xffu] ^ L.h[ent.y >> 24];
-    }
+    const S v0 = L.T[ent.x & 0xffu];
+    const S v1 = L.h[(ent.x >> 8) & 0xffu];
+    const S v2 = L.h[(ent.x >> 16) & 0xffu];
+    const S v3 = L.h[ent.x >> 24];
+    S v = v0 ^ v1 ^ v2 ^ v3;
+    if (ballot(ent.y != 0u) != 0ull)
+        v ^= L.h[ent.y & 0xffu] ^ L.h[(ent.y >> 8) & 0xffu] ^ L.h[(ent.y >> 16) & 0xffu] ^ L.h[ent.y >> 24];
     return v;
 }
 
@@ -326,7 +432,7 @@ template <int NK, bool ORDERED, typename S>
 __device__ __forceinline__ bool light_block(
     const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
     BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
-    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
+    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy)
 {
     const int lane = lane_id();
     const int n = c.n;
@@ -362,7 +468,6 @@ __device__ __forceinline__ bool light_block(
         // the first three steps' entries do not depend on the block's order of
         // reliability: they load while the ranks are sorted
         uint2 e0 = entries(0), e1 = entries(1), e2 = entries(2), e3 = make_uint2(0u, 0u);
-        rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
         uint32_t t = 0;
         // One step: load the entries of step t + 3, test those of step t.
         // Returns 0 (go on), 1 (hit), 2 (no hit, nothing left), 3 (split point).
@@ -386,12 +491,33 @@ __device__ __forceinline__ bool light_block(
             if (split_steps != 0 && t >= split_steps) return 3;
             return 0;
         };
-        int r;
-        for (;;) {
-            if ((r = step(e0, e3)) != 0) break;
-            if ((r = step(e1, e0)) != 0) break;
-            if ((r = step(e2, e1)) != 0) break;
-            if ((r = step(e3, e2)) != 0) break;
+        // Plain order: most blocks end in the first batch, which only reaches
+        // ranks 1..rdepth0, so those ranks are found first (rank_first) and the
+        // first step runs on them; the whole block is ranked only if it goes on.
+        // Whether to try: a per-wave score of how often the first batch decided
+        // (decays by 1/8 per try, +32 per success, so it tends to 256 x the
+        // success rate); below 5/8 it pays to rank the whole block at once, but
+        // every 8th block still tries so that the score follows the channel.
+        int r = 0;
+        bool resume = false;                  // step 0 already tested
+        uint32_t idx1 = 0;
+        lazy.tries = uniform_u32(lazy.tries + 1u);
+        if (!ORDERED && (lazy.score >= 160u || (lazy.tries & 7u) == 0u) &&
+            rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
+            first_tables<S>(idx1, c.rdepth0, cols, s0, L);
+            r = step(e0, e3);
+            resume = true;
+            lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
+        }
+        if (r == 0) {
+            rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
+            for (;;) {
+                if (!resume && (r = step(e0, e3)) != 0) break;
+                resume = false;
+                if ((r = step(e1, e0)) != 0) break;
+                if ((r = step(e2, e1)) != 0) break;
+                if ((r = step(e3, e2)) != 0) break;
+            }
         }
         // the entries prefetched for steps that will not run are taken here, so
         // their registers are free when the next block's code reuses them (no
@@ -415,10 +541,12 @@ template <int NK, bool ORDERED, typename S>
 __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (&hrow)[NK], uint32_t ordv,
                                           const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
                                           uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
-                                          uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy)
+                                          uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy,
+                                          LazyState& lazy)
 {
     const bool left = light_block<NK, ORDERED, S>(x, hrow, c, cols, L, budget, split_steps, ordv,
-                                                  make_buf(cw + row, (uint32_t)c.n), queries + b, abandoned + b);
+                                                  make_buf(cw + row, (uint32_t)c.n), queries + b, abandoned + b,
+                                                  lazy);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
         heavy[slot] = b;
@@ -479,8 +607,14 @@ struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; 
 //   2. the other blocks (a 64-bit mask) are decoded one by one, the next one's
 //      row loaded while the current one is decoded; the two fetch buffers
 //      alternate, so no register copy waits for a load.
+// Waves per SIMD the light pass asks the register allocator for: the device
+// holds 8 (32 per CU); up to 4 keys per lane with 32-bit syndromes fit 64
+// vector registers, wider variants keep the compiler's choice.
+template <int NKMAX, typename S>
+constexpr int light_waves() { return (NKMAX <= 4 && sizeof(S) == 4) ? 8 : 1; }
+
 template <int NKMAX, bool ORDERED, typename S, bool MIXED>
-__global__ void __launch_bounds__(ORBG_WAVE)
+__global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(light_waves<NKMAX, S>())))
 light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
              const float* __restrict__ llr, int64_t nblocks, uint32_t budget, uint32_t split_steps,
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
@@ -500,6 +634,9 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     }
     wave_lds_sync();
     const int lane = lane_id();
+    // rank_first's threshold (start at |LLR| = 2) and try policy, carried from
+    // block to block
+    LazyState lazy = {0x40000000u, 256u, 0u};
     // one code with at most 4 words per row: the rows stay in registers
     constexpr bool HOIST = !MIXED && NKMAX <= 4;
     uint64_t hrow0[NKMAX];
@@ -619,23 +756,23 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         const S* cols = s_cols + (MIXED ? c.col_base : 0);
         if (HOIST) {
             light_one<NKMAX, ORDERED, S>(f.x, hrow0, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw,
-                                         queries, abandoned, ctrs, heavy);
+                                         queries, abandoned, ctrs, heavy, lazy);
         } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
             uint64_t hr[NKMAX];
             load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);
             light_one<NKMAX, ORDERED, S>(f.x, hr, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw, queries,
-                                         abandoned, ctrs, heavy);
+                                         abandoned, ctrs, heavy, lazy);
         } else if (c.nk == 1) {
             uint64_t hr[1];
             load_hrows<1>(s_rows + c.row_base, c.m, hr);
             light_one<1, ORDERED, S>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, b, f.row,
-                                     budget, split_steps, cw, queries, abandoned, ctrs, heavy);
+                                     budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy);
         } else {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
             uint64_t hr[K2];
             load_hrows<K2>(s_rows + c.row_base, c.m, hr);
             light_one<K2, ORDERED, S>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L, b,
-                                      f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy);
+                                      f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy);
         }
     };
 

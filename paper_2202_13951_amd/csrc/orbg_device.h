@@ -183,11 +183,11 @@ __device__ __forceinline__ void bitonic_step32(uint32_t (&key)[NK])
     if constexpr (D > 1) bitonic_step32<NK, SIZE, D / 2>(key);
 }
 
-template <int NK, int SIZE>
+template <int NK, int SIZE, int MAXSIZE>
 __device__ __forceinline__ void bitonic_stage32(uint32_t (&key)[NK])
 {
     bitonic_step32<NK, SIZE, SIZE / 2>(key);
-    if constexpr (SIZE < ORBG_WAVE * NK) bitonic_stage32<NK, SIZE * 2>(key);
+    if constexpr (SIZE < MAXSIZE) bitonic_stage32<NK, SIZE * 2, MAXSIZE>(key);
 }
 
 // Ascending bitonic sort of 64*NK distinct u32 keys, element e = lane * NK + j
@@ -198,7 +198,15 @@ __device__ __forceinline__ void bitonic_stage32(uint32_t (&key)[NK])
 template <int NK>
 __device__ __forceinline__ void bitonic_sort32(uint32_t (&key)[NK])
 {
-    bitonic_stage32<NK, 2>(key);
+    bitonic_stage32<NK, 2, ORBG_WAVE * NK>(key);
+}
+
+// One key per lane, the first log2(GROUP) stages of the same network: lanes
+// 0..GROUP-1 end sorted ascending (the following groups alternate direction).
+template <int GROUP>
+__device__ __forceinline__ void bitonic_sort32_groups(uint32_t (&key)[1])
+{
+    bitonic_stage32<1, 2, GROUP>(key);
 }
 
 }  // namespace orbg

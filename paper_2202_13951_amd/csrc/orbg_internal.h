@@ -33,6 +33,7 @@ struct Schedule {
                         // bytes 1..7 = ranks above 8, ascending, 0 = none
     uint64_t nbatch;
     int rmax;           // largest rank any entry references
+    int rmax0;          // largest rank an entry of the first batch of 64 references
     int wlast;          // logistic weight of the last entry
 };
 

@@ -14,6 +14,7 @@ struct CodeDesc {
     int m;                     // n - k
     int nk;                    // keys per lane of the rank sort: power of two >= n / 64
     int rdepth;                // ranks whose columns are staged (<= 255)
+    int rdepth0;               // ranks the first batch of 64 entries reaches
     uint32_t slen;             // schedule entries
     uint32_t col_base;         // first column of this code in the launch's LDS column table
     uint32_t row_base;         // first word of this code's rows in the launch's LDS row table

@@ -133,7 +133,8 @@ __global__ void class_fill_kernel(int n, uint64_t len, const ClassInfo* classes,
     }
 }
 
-// Deepest rank referenced by the first `len` entries (one thread per batch of 64).
+// Deepest rank referenced by the first `len` entries (one thread per batch of
+// 64), and by the first batch alone (rmax[1]).
 __global__ void rank_depth_kernel(const uint2* entries, uint64_t len, uint64_t nbatch, int* rmax)
 {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,6 +154,7 @@ __global__ void rank_depth_kernel(const uint2* entries, uint64_t len, uint64_t n
         }
     }
     atomicMax(rmax, r);
+    if (b == 0) rmax[1] = r;
 }
 
 __global__ void unpack_kernel(const uint2* entries, uint64_t count, uint8_t* out)
@@ -212,8 +214,8 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * nbatch * 64, stream);
     class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, len, d_classes, nclass, d_entries);
     rank_depth_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, nbatch, d_small + 2);
-    int rmax = 0;
-    (void)hipMemcpyAsync(&rmax, d_small + 2, sizeof(int), hipMemcpyDeviceToHost, stream);
+    int rmax[2] = {0, 0};
+    (void)hipMemcpyAsync(rmax, d_small + 2, sizeof(int) * 2, hipMemcpyDeviceToHost, stream);
     if (hipStreamSynchronize(stream) != hipSuccess) {
         snprintf(err, errlen, "schedule: fill kernels failed: %s", hipGetErrorString(hipGetLastError()));
         (void)hipFree(d_entries); (void)hipFree(d_classes); (void)hipFree(d_small);
@@ -225,7 +227,8 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     out->len = len;
     out->entries = d_entries;
     out->nbatch = nbatch;
-    out->rmax = rmax;
+    out->rmax = rmax[0];
+    out->rmax0 = rmax[1];
     out->wlast = host_small[1];
     return 0;
 }
