@@ -458,12 +458,11 @@ __device__ __forceinline__ bool light_block(
         const uint32_t lim = min(budget, slen);
         const uint32_t T = (lim + ORBG_WAVE - 1) / ORBG_WAVE;
         const uint64_t tail = low_lanes(lim - (T - 1) * ORBG_WAVE);
-        // entries of step u (the last step's again past the end, so that every
-        // path issues the same loads)
-        // (a schedule holds whole batches of 64 entries, so no lane reads past it)
+        // entries of step u: a schedule holds whole batches of 64 entries and
+        // ORBG_SCHED_PAD zero batches after its last one, so the loads for up to
+        // three steps past the end stay inside it and need no bounds check
         auto entries = [&](uint32_t u) -> uint2 {
-            const uint32_t bu = batch_at<ORDERED>(ordv, u < T ? u : T - 1);
-            return load_entry(sched + (size_t)bu * ORBG_WAVE, (uint32_t)lane);
+            return load_entry(sched + (size_t)batch_at<ORDERED>(ordv, u) * ORBG_WAVE, (uint32_t)lane);
         };
         // the first three steps' entries do not depend on the block's order of
         // reliability: they load while the ranks are sorted
@@ -473,12 +472,15 @@ __device__ __forceinline__ bool light_block(
         // Returns 0 (go on), 1 (hit), 2 (no hit, nothing left), 3 (split point).
         // Four register sets rotate, so a load is consumed three steps after it
         // was issued.
+        // the search stops at step tend: the end of the queries, or the split
+        // point if that comes first
+        const uint32_t tend = (split_steps != 0 && split_steps < T) ? split_steps : T;
         auto step = [&](const uint2 cur, uint2& ahead) -> int {
             ahead = entries(t + 3);
             const S syn = entry_syndrome<S>(L, cur);
             uint64_t hits = ballot(syn == 0);
-            const bool last = t + 1 >= T;
-            if (last) hits &= tail;
+            const bool end = t + 1 >= tend;
+            if (end && t + 1 >= T) hits &= tail;
             if (hits) {
                 const int wl = __builtin_ctzll(hits);
                 q = t * ORBG_WAVE + wl + 1;
@@ -486,9 +488,8 @@ __device__ __forceinline__ bool light_block(
                 win_hi = __builtin_amdgcn_readlane(cur.y, wl);
                 return 1;
             }
-            if (last) return 2;
             ++t;
-            if (split_steps != 0 && t >= split_steps) return 3;
+            if (end) return t >= T ? 2 : 3;
             return 0;
         };
         // Plain order: most blocks end in the first batch, which only reaches

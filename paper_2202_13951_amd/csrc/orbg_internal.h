@@ -15,6 +15,7 @@
 #define ORBG_LOW_RANKS 8     // ranks 1..8 are flipped through a per-block subset table
 #define ORBG_HIGH_SLOTS 7    // ranks above 8 held by one entry (bytes 1..7)
 #define ORBG_WLEVEL_PACKED 99  // every pattern of logistic weight <= 99 has at most 7 ranks above 8
+#define ORBG_SCHED_PAD 4        // zero batches after a schedule's last batch
 
 namespace orbg {
 

@@ -205,13 +205,16 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     }
     const uint64_t nbatch = (len + 63) / 64;
     uint2* d_entries = nullptr;
-    if (hipMalloc(&d_entries, sizeof(uint2) * nbatch * 64) != hipSuccess) {
+    // ORBG_SCHED_PAD zero batches follow the last one, so a search may load the
+    // entries of a few steps past its end without a bounds check
+    const uint64_t alloc = (nbatch + ORBG_SCHED_PAD) * 64;
+    if (hipMalloc(&d_entries, sizeof(uint2) * alloc) != hipSuccess) {
         snprintf(err, errlen, "schedule: cannot allocate %llu entries", (unsigned long long)len);
         (void)hipFree(d_classes); (void)hipFree(d_small);
         return -2;
     }
     // entries past len (up to the batch boundary) stay zero: the empty pattern
-    (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * nbatch * 64, stream);
+    (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * alloc, stream);
     class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, len, d_classes, nclass, d_entries);
     rank_depth_kernel<<<(unsigned)((nbatch + 255) / 256), 256, 0, stream>>>(d_entries, len, nbatch, d_small + 2);
     int rmax[2] = {0, 0};
