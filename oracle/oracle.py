@@ -58,6 +58,13 @@ def lib():
         L.oracle_is_codeword.argtypes = [u8p, ctypes.c_int, ctypes.c_int, u8p]
         L.oracle_permutation.restype = None
         L.oracle_permutation.argtypes = [u8p, ctypes.c_int, i32p]
+        L.oracle_order1_prefix.restype = ctypes.c_long
+        L.oracle_order1_prefix.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_int, i32p, i32p]
+        L.oracle_fit_j0.restype = ctypes.c_long
+        L.oracle_fit_j0.argtypes = [u8p, ctypes.c_int]
+        L.oracle_decode_1line.restype = ctypes.c_int
+        L.oracle_decode_1line.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_long,
+                                          u8p, u8p, u8p, u8p, ctypes.c_long, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -155,3 +162,42 @@ def permutation(llr: np.ndarray) -> np.ndarray:
     pi = np.zeros(n, dtype=np.int32)
     lib().oracle_permutation(_ptr(llr), n, pi.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     return pi
+
+
+# ---------------------------------------------------------------------------
+# 1-line ORBGRAND (Sec. IV with one segment; readings R10, R11 in the C source)
+# ---------------------------------------------------------------------------
+NO_FORCE = -(1 << 63)
+
+
+def order1_prefix(n: int, j0: int, count: int) -> list[tuple[int, ...]]:
+    """First `count` patterns of the 1-line order for (n, J0), as rank tuples."""
+    L = lib()
+    out = np.zeros((count, WIDTH), dtype=np.int32)
+    wout = np.zeros(count, dtype=np.int32)
+    got = L.oracle_order1_prefix(n, j0, count, WIDTH, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 wout.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    assert got >= 0, got
+    return [tuple(int(x) for x in out[g, :wout[g]]) for g in range(got)]
+
+
+def fit_j0(llr: np.ndarray) -> int:
+    """J0 of one block (1-D float32 LLRs)."""
+    x = np.ascontiguousarray(llr, dtype=np.float32)
+    return int(lib().oracle_fit_j0(_ptr(x), x.shape[0]))
+
+
+def decode_1line(H: np.ndarray, llr: np.ndarray, budget: int, threads: int = 1, j0_force: int | None = None):
+    """1-line ORBGRAND decode; returns (codewords u8 [N, n], queries u64 [N], abandoned u8 [N], J0 i32 [N])."""
+    H = np.ascontiguousarray(H, dtype=np.uint8)
+    llr = np.ascontiguousarray(llr, dtype=np.float32)
+    N, n = llr.shape
+    k = n - H.shape[0]
+    cw = np.zeros((N, n), dtype=np.uint8)
+    q = np.zeros(N, dtype=np.uint64)
+    ab = np.zeros(N, dtype=np.uint8)
+    j0 = np.zeros(N, dtype=np.int32)
+    rc = lib().oracle_decode_1line(_ptr(H), _ptr(llr), n, k, budget, N, _ptr(cw), _ptr(q), _ptr(ab), _ptr(j0),
+                                   NO_FORCE if j0_force is None else int(j0_force), threads)
+    assert rc == 0, rc
+    return cw, q, ab, j0

@@ -41,6 +41,21 @@
  * batch), then the plain order continues from g = 4096.  The budget and the
  * abandonment rule are unchanged.
  *
+ * 1-line ORBGRAND (the full ORBGRAND of Sec. IV with m = 1 segment): the
+ * reliability of rank j is modelled as J0 + beta j (eq. (relest_seg)), so a
+ * pattern's reliability weight is J0 w + beta W (eq. (W2IJ)) with w its Hamming
+ * and W its logistic weight; patterns are taken by increasing reliability
+ * weight, and inside one weight by the rules above.  Fitting and quantization
+ * (Sec. IV, eqs. (Q), (quant)) with m = 1:
+ *   R10 the anchor points are ranks 1 and h = floor(n/2) and the one line joins
+ *       them (the central line extended over the whole curve), so
+ *       Q = (L_h - L_1) / (h - 1), beta = [Q / Q] = 1 and J0 = [L_1 / Q] - 1,
+ *       L_j the j-th smallest |LLR|; with beta = 1 the weight is J0 w + W;
+ *   R11 [x] rounds half up, floor(x + 1/2); the fit runs in FP32 in exactly
+ *       this order; Q <= 0, NaN or infinite values give J0 = 0 (basic
+ *       ORBGRAND), and J0 is capped at 2^20 (far beyond any weight reached).
+ *   With J0 = 0 the order is the basic one.
+ *
  * Parity status: every function here is pinned by tests (brute-force
  * enumeration, closed forms, the paper's worked partition example and first
  * queries, brute-force ML over all codewords of tiny codes).
@@ -49,6 +64,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <limits.h>
 
 #define ORACLE_NMAX 1024
 
@@ -195,6 +211,74 @@ static int order_next(orb_order_t* o, int* v, int* wout)
             int np = o->n - o->w;                              /* n' */
             if (Wp <= (long)o->w * np &&
                 landslide_init(&o->ls, (int)Wp, o->w, np))
+                o->active = 1;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1-line order: classes (W, w) taken by increasing J0 w + W, then w.         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;
+    long J0;
+    long C;          /* current reliability weight J0 w + W                  */
+    int w;           /* current Hamming weight                              */
+    int empty_done;
+    int active;
+    landslide_t ls;
+} orb1_order_t;
+
+/* Smallest and largest logistic weight of w distinct ranks in [1, n]. */
+static long lw_min(int w) { return (long)w * (w + 1) / 2; }
+static long lw_max(int w, int n) { return (long)w * n - (long)w * (w - 1) / 2; }
+
+static void order1_init(orb1_order_t* o, int n, long J0)
+{
+    memset(o, 0, sizeof(*o));
+    o->n = n;
+    o->J0 = J0;
+    o->C = 0;
+    o->w = 0;
+}
+
+/* Next pattern of the 1-line order (same output convention as order_next). */
+static int order1_next(orb1_order_t* o, int* v, int* wout)
+{
+    int u[ORACLE_NMAX];
+    int i;
+    if (!o->empty_done) { o->empty_done = 1; *wout = 0; return 1; }   /* weight 0, w = 0 first */
+    for (;;) {
+        if (o->active && landslide_next(&o->ls, u)) {
+            for (i = 0; i < o->w; ++i) v[i] = u[i] + i + 1;
+            *wout = o->w;
+            return 1;
+        }
+        o->active = 0;
+        /* advance (C, w): w ascending while some w can still reach C */
+        for (;;) {
+            o->w += 1;
+            if (o->w <= o->n && lw_min(o->w) + o->J0 * o->w <= o->C) break;
+            /* no larger w at this weight: next weight that some w can reach */
+            {
+                long next = -1;
+                int ww;
+                for (ww = 1; ww <= o->n; ++ww) {
+                    long lo = o->J0 * ww + lw_min(ww), hi = o->J0 * ww + lw_max(ww, o->n);
+                    long c = (o->C + 1 > lo) ? o->C + 1 : lo;
+                    if (c <= hi && (next < 0 || c < next)) next = c;
+                }
+                if (next < 0) return 0;                 /* all 2^n patterns done */
+                o->C = next;
+                o->w = 0;
+            }
+        }
+        {
+            long W = o->C - o->J0 * o->w;              /* logistic weight of the class */
+            long Wp = W - lw_min(o->w);
+            int np = o->n - o->w;
+            if (Wp >= 0 && Wp <= (long)o->w * np && landslide_init(&o->ls, (int)Wp, o->w, np))
                 o->active = 1;
         }
     }
@@ -409,6 +493,114 @@ int oracle_decode_ordered(const uint8_t* H, const float* llr, int n, int k, uint
         decode_one(H, llr + (size_t)b * n, n, k, budget, order + (size_t)b * 64,
                    cw + (size_t)b * n, queries + b, abandoned + b);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1-line ORBGRAND decoder.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* J0 of one block from its reliability order (readings R10, R11). */
+static long fit_j0(const float* llr, const int* pi, int n)
+{
+    int h = n / 2;
+    float L1, Lh, Q, r;
+    if (h < 2) return 0;
+    L1 = fabsf(llr[pi[0]]);
+    Lh = fabsf(llr[pi[h - 1]]);
+    Q = (Lh - L1) / (float)(h - 1);
+    if (!(Q > 0.0f) || !isfinite(Q)) return 0;
+    r = L1 / Q;
+    if (!isfinite(r)) return 0;
+    r = floorf(r + 0.5f);
+    if (r > 1048576.0f) r = 1048576.0f;
+    return (long)r - 1;
+}
+
+static int decode_one_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                            long j0_force, uint8_t* cw, uint64_t* queries, uint8_t* abandoned,
+                            int32_t* j0_out)
+{
+    int m = n - k;
+    int i, w;
+    int v[ORACLE_NMAX];
+    int* pi = (int*)malloc(sizeof(int) * (size_t)n);
+    uint8_t* y = (uint8_t*)malloc((size_t)n);
+    uint8_t* x = (uint8_t*)malloc((size_t)n);
+    orb1_order_t* o = (orb1_order_t*)malloc(sizeof(orb1_order_t));
+    uint64_t q = 0;
+    int found = 0;
+    long J0;
+
+    for (i = 0; i < n; ++i) y[i] = (llr[i] > 0.0f) ? 1 : 0;
+    reliability_permutation(llr, n, pi);
+    J0 = (j0_force != LONG_MIN) ? j0_force : fit_j0(llr, pi, n);
+    if (j0_out) *j0_out = (int32_t)J0;
+    order1_init(o, n, J0);
+    while (q < budget && order1_next(o, v, &w)) {
+        ++q;
+        memcpy(x, y, (size_t)n);
+        for (i = 0; i < w; ++i) x[pi[v[i] - 1]] ^= 1;
+        if (in_codebook(H, m, n, x)) { found = 1; break; }
+    }
+    if (found) {
+        memcpy(cw, x, (size_t)n);
+        *queries = q;
+        *abandoned = 0;
+    } else {
+        memcpy(cw, y, (size_t)n);
+        *queries = budget;
+        *abandoned = 1;
+    }
+    free(o); free(pi); free(y); free(x);
+    return 0;
+}
+
+/* 1-line decode of `batch` blocks (layout as oracle_decode).  j0_out (may be
+ * NULL) receives each block's J0; j0_force != LONG_MIN replaces the fit by
+ * that value for every block (tests of the order alone). */
+int oracle_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, long batch,
+                        uint8_t* cw, uint64_t* queries, uint8_t* abandoned, int32_t* j0_out,
+                        long j0_force, int threads)
+{
+    long b;
+    if (check_args(H, llr, n, k, budget) != 0 || batch < 0) return -1;
+    if (j0_force != LONG_MIN && (j0_force < -1 || j0_force > 1048575)) return -1;
+    (void)threads;
+#pragma omp parallel for schedule(static) num_threads(threads > 0 ? threads : 1)
+    for (b = 0; b < batch; ++b)
+        decode_one_1line(H, llr + (size_t)b * n, n, k, budget, j0_force, cw + (size_t)b * n,
+                         queries + b, abandoned + b, j0_out ? j0_out + b : NULL);
+    return 0;
+}
+
+/* First `count` patterns of the 1-line order for (n, J0), as oracle_order_prefix. */
+long oracle_order1_prefix(int n, long j0, long count, int width, int* out, int* wout)
+{
+    orb1_order_t* o = (orb1_order_t*)malloc(sizeof(orb1_order_t));
+    int v[ORACLE_NMAX];
+    int w, i;
+    long g = 0;
+    if (!o) return -2;
+    order1_init(o, n, j0);
+    while (g < count && order1_next(o, v, &w)) {
+        if (w > width) { free(o); return -1; }
+        for (i = 0; i < width; ++i) out[g * width + i] = (i < w) ? v[i] : 0;
+        wout[g] = w;
+        ++g;
+    }
+    free(o);
+    return g;
+}
+
+/* The 1-line fit alone: J0 of one block. */
+long oracle_fit_j0(const float* llr, int n)
+{
+    int* pi = (int*)malloc(sizeof(int) * (size_t)n);
+    long j0;
+    reliability_permutation(llr, n, pi);
+    j0 = fit_j0(llr, pi, n);
+    free(pi);
+    return j0;
 }
 
 /* Syndrome-free membership test exposed for the invariant tests. */
