@@ -113,6 +113,40 @@ int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t bu
                    uint8_t* abandoned, const orbg_launch_params* params, void* stream);
 
 /*
+ * 1-line ORBGRAND decode (the one-segment case of the full ORBGRAND model of
+ * Sec. IV, noted there as giving a small gain over the basic order).
+ *
+ * Each block's reliability curve is fitted with one line through its anchors at
+ * ranks 1 and h = floor(n / 2) (Sec. IV, anchor-point fitting): slope
+ * Q = (L_h - L_1) / (h - 1), with L_j the |LLR| of rank j; quantised offset
+ * J0 = [L_1 / Q] - 1, [x] = floor(x + 1/2) (eqs. (Q) and (quant) with m = 1,
+ * beta = 1); each operation is FP32 rounded to nearest in that order.  A slope
+ * that is not positive and finite, or a ratio L_1 / Q that is not finite, gives
+ * J0 = 0, the basic order; [L_1 / Q] is capped at 2^20.  Patterns are then
+ * tested by increasing reliability weight J0 w + W (eq. (W2IJ): w Hamming
+ * weight, W logistic weight), inside one weight by increasing w, inside one
+ * (W, w) in Landslide order.  Ranks, membership test, budget, abandonment and
+ * outputs are as in orbg_decode; results depend on neither `params` nor
+ * timing.
+ *
+ * j0: DEVICE int32 per block receiving the fitted J0, or NULL (then blocks
+ * whose hard decision is already a codeword are not ranked).
+ * The first call for an (n, budget rounded up to a multiple of 64) builds one
+ * schedule per offset J0 = -1 .. j0max, where j0max is the largest logistic
+ * weight among the first `budget` patterns taken by Hamming weight first: from
+ * there on every J0 tests the same first `budget` patterns in the same order,
+ * so larger fitted offsets decode with the schedule of j0max.  That takes
+ * (j0max + 2) x 8 x budget bytes of device memory (about 0.2 GB for n = 127,
+ * budget 10^5).  Returns ORBG_EINVAL when those patterns reach a logistic
+ * weight above 255, or flip more than 7 ranks above 8 at logistic weight 100
+ * or more (e.g. n = 256 with a budget above 256, n = 127 with a budget above
+ * about 2.86 x 10^5).
+ */
+int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                      int64_t batch, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                      int32_t* j0, const orbg_launch_params* params, void* stream);
+
+/*
  * Registers a parity-check matrix (host, as for orbg_decode) for mixed-code
  * decodes and returns its id in *code_id.  Registering the same H twice gives
  * two ids for one cached copy.  Allocates and synchronises the device on first
@@ -149,6 +183,16 @@ int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code,
  * 1 <= count <= 2^22 and count <= 2^n.  Synchronises `stream`.
  */
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream);
+
+/*
+ * As orbg_schedule_export for the 1-line order of offset j0 (-1 <= j0 < 2^20)
+ * that orbg_decode_1line uses with this `budget` (1 <= budget <= 2^22,
+ * budget <= 2^n): the first `count` <= budget entries of the schedule of
+ * min(j0, j0max).  *j0max (if not NULL) receives j0max.  count = 0 only builds
+ * the schedules.  Errors as for orbg_decode_1line.  Synchronises `stream`.
+ */
+int orbg_schedule_export_1line(int n, uint64_t budget, int j0, uint64_t count, uint8_t* out,
+                               int* j0max, void* stream);
 
 /*
  * Learned batch-order proposal (an addition to the paper's method, used through

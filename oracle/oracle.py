@@ -181,6 +181,18 @@ def order1_prefix(n: int, j0: int, count: int) -> list[tuple[int, ...]]:
     return [tuple(int(x) for x in out[g, :wout[g]]) for g in range(got)]
 
 
+def order1_prefix_array(n: int, j0: int, count: int) -> np.ndarray:
+    """First `count` 1-line patterns as an int32 [count, 16] array of ranks (zero padded)."""
+    L = lib()
+    out = np.zeros((count, WIDTH), dtype=np.int32)
+    wout = np.zeros(count, dtype=np.int32)
+    got = L.oracle_order1_prefix(n, j0, count, WIDTH, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 wout.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    if got < 0:
+        raise ValueError("pattern wider than the row width")
+    return out[:got]
+
+
 def fit_j0(llr: np.ndarray) -> int:
     """J0 of one block (1-D float32 LLRs)."""
     x = np.ascontiguousarray(llr, dtype=np.float32)

@@ -75,6 +75,10 @@ def load():
     L.orbg_mlp_order.restype = ci
     L.orbg_schedule_export.argtypes = [ci, u64, vp, vp]
     L.orbg_schedule_export.restype = ci
+    L.orbg_decode_1line.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp, vp, vp]
+    L.orbg_decode_1line.restype = ci
+    L.orbg_schedule_export_1line.argtypes = [ci, u64, ci, u64, vp, ctypes.POINTER(ci), vp]
+    L.orbg_schedule_export_1line.restype = ci
     L.orbg_last_error.argtypes = []
     L.orbg_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -166,6 +170,30 @@ def orbg_decode_ex(H, llr, budget: int, order=None, params: LaunchParams | None 
     return cw, q, ab
 
 
+def orbg_decode_1line(H, llr, budget: int, j0=True, params: LaunchParams | None = None, out=None, stream=None):
+    """1-line ORBGRAND decode.  j0: True (allocate), a CUDA int32 [N] tensor, or None/False
+    (offsets not reported).  Returns (codeword, queries, abandoned, j0 or None)."""
+    import torch
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    assert llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()
+    assert llr.dim() == 2 and llr.shape[1] == n
+    N = llr.shape[0]
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    if j0 is True:
+        j0 = torch.empty((N,), dtype=torch.int32, device=llr.device)
+    elif j0 is False:
+        j0 = None
+    if j0 is not None:
+        assert j0.is_cuda and j0.dtype == torch.int32 and j0.is_contiguous() and j0.shape[0] == N
+    rc = load().orbg_decode_1line(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
+                                  int(budget), N, ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
+                                  ctypes.c_void_p(ab.data_ptr()), _p(j0), _params_ptr(params),
+                                  _stream_ptr(stream))
+    _check("orbg_decode_1line", rc)
+    return cw, q, ab, j0
+
+
 def orbg_code_register(H) -> int:
     """Registers a parity-check matrix for mixed decodes; returns its id."""
     Hn = _host_H(H)
@@ -205,6 +233,18 @@ def orbg_schedule_export(n: int, count: int, stream=None) -> np.ndarray:
                                      _stream_ptr(stream))
     _check("orbg_schedule_export", rc)
     return out
+
+
+def orbg_schedule_export_1line(n: int, budget: int, j0: int, count: int, stream=None):
+    """The first `count` entries of the 1-line schedule of offset j0 used with this budget:
+    (uint8 [count, 16] of ranks, j0max)."""
+    out = np.zeros((max(count, 1), 16), dtype=np.uint8)
+    jm = ctypes.c_int(-2)
+    rc = load().orbg_schedule_export_1line(int(n), int(budget), int(j0), int(count),
+                                           out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(jm),
+                                           _stream_ptr(stream))
+    _check("orbg_schedule_export_1line", rc)
+    return out[:count], jm.value
 
 
 # ---------------------------------------------------------------------------

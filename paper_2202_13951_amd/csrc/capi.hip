@@ -56,6 +56,8 @@ std::map<std::pair<int, uint64_t>, std::vector<CodeEntry*>> g_codes;
 std::vector<CodeEntry*> g_registry;
 // (device, n, len) -> schedule
 std::map<std::tuple<int, int, uint64_t>, orbg::Schedule*> g_sched;
+// (device, n, len) -> 1-line schedules
+std::map<std::tuple<int, int, uint64_t>, orbg::Schedule1*> g_sched1;
 // (device, stream) -> work space
 std::map<std::pair<int, hipStream_t>, Workspace> g_work;
 // device -> compute units
@@ -160,6 +162,30 @@ int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule*
     return ORBG_OK;
 }
 
+// 1-line schedules with at least `need` entries for length n (need <= 2^n):
+// lengths are whole batches of 64, so budgets within one batch share them.
+int get_schedule_1line(int n, uint64_t need, hipStream_t stream, const orbg::Schedule1** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
+    uint64_t len = (need + 63) / 64 * 64;
+    if (n < 63 && len > (1ull << n)) len = 1ull << n;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(dev, n, len);
+    auto it = g_sched1.find(key);
+    if (it != g_sched1.end()) { *out = it->second; return ORBG_OK; }
+    orbg::Schedule1* s = new orbg::Schedule1;
+    char err[256] = {0};
+    const int rc = orbg_build_schedule_1line(n, len, stream, s, err, sizeof(err));
+    if (rc != 0) {
+        delete s;
+        return fail(rc == -2 ? ORBG_ENOMEM : (rc == -1 ? ORBG_EINVAL : ORBG_EHIP), "%s", err);
+    }
+    g_sched1[key] = s;
+    *out = s;
+    return ORBG_OK;
+}
+
 // Per-stream counters and heavy-block list (calls on one stream are ordered,
 // so they can share them).  Grows the list to `heavy_need` entries.
 int get_workspace(hipStream_t st, int64_t heavy_need, Workspace** out, int* cus)
@@ -257,6 +283,29 @@ int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_bas
     return ORBG_OK;
 }
 
+// Code descriptor of a 1-line decode (schedules for `need` queries).
+int describe_1line(const CodeEntry* c, uint64_t need, hipStream_t st, orbg::CodeDesc* d)
+{
+    if (c->n < 63 && need > (1ull << c->n)) need = 1ull << c->n;
+    const orbg::Schedule1* s = nullptr;
+    int rc = get_schedule_1line(c->n, need, st, &s);
+    if (rc) return rc;
+    d->n = c->n;
+    d->m = c->n - c->k;
+    d->nk = keys_per_lane(c->n);
+    d->rdepth = s->rmax < c->n ? s->rmax : c->n;
+    d->rdepth0 = d->rdepth;
+    d->slen = (uint32_t)s->len;
+    d->col_base = 0;
+    d->cols = c->d_cols;
+    d->rows = c->d_rows;
+    d->row_base = 0;
+    d->sched = s->entries;
+    d->j0max = s->j0max;
+    d->sstride = (uint32_t)s->stride;
+    return ORBG_OK;
+}
+
 int check_budget(uint64_t budget, int64_t batch)
 {
     if (budget < 1 || budget > ORBG_BUDGET_MAX)
@@ -267,7 +316,7 @@ int check_budget(uint64_t budget, int64_t batch)
 
 int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
-                  const orbg_launch_params* params, void* stream)
+                  const orbg_launch_params* params, void* stream, bool oneline = false, int32_t* j0 = nullptr)
 {
     int rc = check_code_args(H, n, k);
     if (rc) return rc;
@@ -281,7 +330,9 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     orbg::DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.codes.ncodes = 1;
-    if ((rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]))) return rc;
+    if (oneline) rc = describe_1line(code, budget, st, &a.codes.c[0]);
+    else rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]);
+    if (rc) return rc;
     a.codes.rwords = a.codes.c[0].m * a.codes.c[0].nk;
     if (batch == 0) return ORBG_OK;
     a.p = resolve_params(params, order != nullptr);
@@ -292,6 +343,8 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     a.nblocks = batch;
     a.budget = (uint32_t)budget;
     a.order = order;
+    a.oneline = oneline;
+    a.j0 = j0;
     a.cw = codeword;
     a.queries = queries;
     a.abandoned = abandoned;
@@ -328,6 +381,15 @@ int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t bu
 {
     g_err.clear();
     return decode_single(H, llr, n, k, budget, batch, order, codeword, queries, abandoned, params, stream);
+}
+
+int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                      uint8_t* codeword, uint64_t* queries, uint8_t* abandoned, int32_t* j0,
+                      const orbg_launch_params* params, void* stream)
+{
+    g_err.clear();
+    return decode_single(H, llr, n, k, budget, batch, nullptr, codeword, queries, abandoned, params, stream, true,
+                         j0);
 }
 
 int orbg_code_register(const uint8_t* H, int n, int k, int* code_id)
@@ -430,6 +492,33 @@ int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)
     uint8_t* d_out = nullptr;
     if (hipMalloc(&d_out, 16 * count) != hipSuccess) return fail(ORBG_ENOMEM, "cannot allocate export buffer");
     const bool ok = orbg::orbg_unpack_schedule(s, count, d_out, st) == 0 &&
+                    hipMemcpyAsync(out, d_out, 16 * count, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                    hipStreamSynchronize(st) == hipSuccess;
+    (void)hipFree(d_out);
+    if (!ok) return fail(ORBG_EHIP, "schedule export failed");
+    return ORBG_OK;
+}
+
+int orbg_schedule_export_1line(int n, uint64_t budget, int j0, uint64_t count, uint8_t* out, int* j0max,
+                               void* stream)
+{
+    g_err.clear();
+    if (n < 1 || n > ORBG_NMAX) return fail(ORBG_EINVAL, "n = %d outside [1, %d]", n, ORBG_NMAX);
+    if (budget < 1 || budget > ORBG_BUDGET_MAX || (n < 63 && budget > (1ull << n)))
+        return fail(ORBG_EINVAL, "budget = %llu out of range", (unsigned long long)budget);
+    if (count > budget) return fail(ORBG_EINVAL, "count = %llu above the budget", (unsigned long long)count);
+    if (j0 < -1 || j0 >= (1 << 20)) return fail(ORBG_EINVAL, "j0 = %d outside [-1, 2^20 - 1]", j0);
+    if (count > 0 && !out) return fail(ORBG_EINVAL, "out is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const orbg::Schedule1* s = nullptr;
+    int rc = get_schedule_1line(n, budget, st, &s);
+    if (rc) return rc;
+    if (j0max) *j0max = s->j0max;
+    if (count == 0) return ORBG_OK;
+    const int jc = j0 < s->j0max ? j0 : s->j0max;
+    uint8_t* d_out = nullptr;
+    if (hipMalloc(&d_out, 16 * count) != hipSuccess) return fail(ORBG_ENOMEM, "cannot allocate export buffer");
+    const bool ok = orbg::orbg_unpack_entries(s->entries + (size_t)(jc + 1) * s->stride, count, d_out, st) == 0 &&
                     hipMemcpyAsync(out, d_out, 16 * count, hipMemcpyDeviceToHost, st) == hipSuccess &&
                     hipStreamSynchronize(st) == hipSuccess;
     (void)hipFree(d_out);

@@ -175,9 +175,11 @@ struct IndexBits { static constexpr int value = NK == 1 ? 6 : NK == 2 ? 7 : NK =
 // is the order of the full keys (bits of |LLR|) << 32 | index except inside runs
 // of equal truncated magnitudes, so if two neighbours among the ranks the
 // schedule reaches share a truncated magnitude, the full 64-bit keys are
-// sorted instead.  Positions past n hold keys above every element.
+// sorted instead; hfit > 0 adds ranks 1 and hfit to the ranks whose element
+// must be exact (their magnitudes fit the 1-line model).  Positions past n hold
+// keys above every element.
 template <int NK>
-__device__ __forceinline__ void rank_order(const float (&x)[NK], int n, int rdepth, uint32_t (&idx)[NK])
+__device__ __forceinline__ void rank_order(const float (&x)[NK], int n, int rdepth, int hfit, uint32_t (&idx)[NK])
 {
     constexpr int IB = IndexBits<NK>::value;
     const int lane = lane_id();
@@ -196,7 +198,8 @@ __device__ __forceinline__ void rank_order(const float (&x)[NK], int n, int rdep
         const int e = lane * NK + j;
         const uint32_t other = (j + 1 < NK) ? key[(j + 1) % NK] : next0;
         const bool has_next = (j + 1 < NK) || lane + 1 < ORBG_WAVE;
-        tie |= has_next && e < rdepth && ((key[j] ^ other) >> IB) == 0u;
+        const bool exact = e < rdepth || (hfit > 0 && (e == 0 || e == hfit - 2 || e == hfit - 1));
+        tie |= has_next && exact && ((key[j] ^ other) >> IB) == 0u;
     }
     if (ballot(tie) != 0ull) {
         uint64_t k64[NK];
@@ -227,6 +230,47 @@ __device__ __forceinline__ uint64_t readlane_s<uint64_t>(uint64_t v, int l)
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
     return ((uint64_t)hi << 32) | lo;
+}
+
+// x of received index i (wave-uniform), read from the lane that holds it.
+template <int NK>
+__device__ __forceinline__ float value_at(const float (&x)[NK], uint32_t i)
+{
+    const uint32_t j = i / ORBG_WAVE;
+    float v = x[0];
+#pragma unroll
+    for (int jj = 1; jj < NK; ++jj) v = (j == (uint32_t)jj) ? x[jj] : v;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)(i % ORBG_WAVE)));
+}
+
+// 1-line fit of the sorted reliabilities (Sec. IV, eqs. (Q) and (quant) with
+// one segment and beta = 1): anchors at ranks 1 and h = floor(n / 2), slope
+// Q = (L_h - L_1) / (h - 1), offset J0 = [L_1 / Q] - 1 with [x] = floor(x + 1/2),
+// each operation rounded to nearest in FP32 in that order.  A slope that is not
+// positive and finite, or an L_1 / Q that is not finite, gives J0 = 0 (the
+// basic order); [L_1 / Q] is capped at 2^20.  idx[j] holds the received index
+// of rank lane * NK + j + 1 (exact for ranks 1 and h).  Returns a wave-uniform
+// value.
+template <int NK>
+__device__ __forceinline__ int fit_offset(const float (&x)[NK], const uint32_t (&idx)[NK], int n)
+{
+    const int h = n / 2;
+    if (h < 2) return 0;
+    const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)idx[0], 0);
+    const int e = h - 1;                                  // rank h sits in lane e / NK, key e % NK
+    uint32_t sel = idx[0];
+#pragma unroll
+    for (int j = 1; j < NK; ++j) sel = (e % NK == j) ? idx[j] : sel;
+    const uint32_t ih = (uint32_t)__builtin_amdgcn_readlane((int)sel, e / NK);
+    const float l1 = fabsf(value_at<NK>(x, i1));
+    const float lh = fabsf(value_at<NK>(x, ih));
+    const float q = __fdiv_rn(__fsub_rn(lh, l1), (float)(h - 1));
+    if (!(q > 0.0f) || !__builtin_isfinite(q)) return 0;
+    float r = __fdiv_rn(l1, q);
+    if (!__builtin_isfinite(r)) return 0;
+    r = floorf(__fadd_rn(r, 0.5f));
+    r = r > 1048576.0f ? 1048576.0f : r;
+    return (int)uniform_u32((uint32_t)((int)r - 1));
 }
 
 // Step 3 for the first batch only: the ra (<= 32) least reliable ranks without
@@ -337,14 +381,16 @@ __device__ __forceinline__ void first_tables(uint32_t idx1, int ra, const S* __r
 // Step 3: reliability order and the per-block lookup tables: h[r] = column of
 // rank r and pi[r] = its received index for the ranks the schedule reaches,
 // T[m] = s0 XOR (XOR of h_r over the bits r - 1 of m) for the 256 subsets of
-// ranks 1..8 (h_1..h_8 taken from the lanes that hold them).
-template <int NK, typename S>
-__device__ __forceinline__ void rank_and_tables(const float (&x)[NK], int n, const S* __restrict__ cols, S s0,
-                                                int rdepth, BlockLds<S>& L)
+// ranks 1..8 (h_1..h_8 taken from the lanes that hold them).  FIT: returns the
+// block's 1-line offset J0 (fit_offset), else 0.
+template <int NK, typename S, bool FIT = false>
+__device__ __forceinline__ int rank_and_tables(const float (&x)[NK], int n, const S* __restrict__ cols, S s0,
+                                               int rdepth, BlockLds<S>& L)
 {
     const int lane = lane_id();
     uint32_t idx[NK];
-    rank_order<NK>(x, n, rdepth, idx);
+    rank_order<NK>(x, n, rdepth, FIT ? n / 2 : 0, idx);
+    const int j0 = FIT ? fit_offset<NK>(x, idx, n) : 0;
     S hv[NK];
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
@@ -368,6 +414,7 @@ __device__ __forceinline__ void rank_and_tables(const float (&x)[NK], int n, con
     L.T[lane + 128] = a ^ hs[7];
     L.T[lane + 192] = a ^ hs[6] ^ hs[7];
     wave_lds_sync();
+    return j0;
 }
 
 // Step 4, one step: syndrome of every lane's entry.  Slots past the entry's
@@ -426,13 +473,29 @@ __device__ __forceinline__ void write_result(uint64_t* q_out, uint8_t* ab_out, u
     __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(abandon ? 1 : 0), make_buf(ab_out, 1), lane, 0, 0);
 }
 
+// Schedule of a 1-line block with fitted offset j0 (offsets above the code's
+// j0max share its last schedule, which orders the first slen patterns alike).
+__device__ __forceinline__ const uint2* oneline_schedule(const CodeDesc& c, int j0)
+{
+    const int jc = j0 < c.j0max ? j0 : c.j0max;
+    return c.sched + (size_t)(jc + 1) * c.sstride;
+}
+
+// The 1-line offset of one block: lane 0's store is the only one inside the
+// 4-byte descriptor.
+__device__ __forceinline__ void write_offset(int32_t* j0_out, int j0)
+{
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)j0, make_buf(j0_out, 4), lane_id() * 4, 0, 0);
+}
+
 // Light pass, one block.  Returns true if the block is left for the heavy pass
-// (then nothing is written).
-template <int NK, bool ORDERED, typename S>
+// (then nothing is written but the 1-line offset).  ONELINE: the block's fitted
+// offset (written to j0_out when that is not null) picks its schedule.
+template <int NK, bool ORDERED, typename S, bool ONELINE>
 __device__ __forceinline__ bool light_block(
     const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
     BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
-    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy)
+    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy, int32_t* __restrict__ j0_out)
 {
     const int lane = lane_id();
     const int n = c.n;
@@ -443,13 +506,21 @@ __device__ __forceinline__ bool light_block(
     uint32_t q = budget;
     uint32_t win_lo = 0, win_hi = 0;     // winning entry (wave-uniform)
 
+    // 1-line: the offset needs the whole ranking, made here when the block needs
+    // a search or its offset is asked for
+    const uint2* __restrict__ sched = c.sched;
+    if (ONELINE && (s0 != 0 || j0_out != nullptr)) {
+        const int j0 = rank_and_tables<NK, S, true>(x, n, cols, s0, c.rdepth, L);
+        if (j0_out != nullptr) write_offset(j0_out, j0);
+        sched = oneline_schedule(c, j0);
+    }
+
     // s0 == 0: the empty pattern (entry 0 of batch 0) is a member; it is the first
-    // hit when batch 0 is tested first (always in the plain order)
+    // hit when batch 0 is tested first (always in the plain and 1-line orders)
     if (s0 == 0 && (!ORDERED || batch_at<ORDERED>(ordv, 0) == 0)) {
         found = true;
         q = 1;
     } else {
-        const uint2* __restrict__ sched = c.sched;
         const uint32_t slen = c.slen;
         // Step t tests batch bt; lane l takes schedule entry 64 bt + l, which is
         // query number 64 t + l + 1.  The queries that exist are the first
@@ -465,7 +536,8 @@ __device__ __forceinline__ bool light_block(
             return load_entry(sched + (size_t)batch_at<ORDERED>(ordv, u) * ORBG_WAVE, (uint32_t)lane);
         };
         // the first three steps' entries do not depend on the block's order of
-        // reliability: they load while the ranks are sorted
+        // reliability: they load while the ranks are sorted (1-line: after the
+        // ranking that picks the schedule)
         uint2 e0 = entries(0), e1 = entries(1), e2 = entries(2), e3 = make_uint2(0u, 0u);
         uint32_t t = 0;
         // One step: load the entries of step t + 3, test those of step t.
@@ -503,7 +575,7 @@ __device__ __forceinline__ bool light_block(
         bool resume = false;                  // step 0 already tested
         uint32_t idx1 = 0;
         lazy.tries = uniform_u32(lazy.tries + 1u);
-        if (!ORDERED && (lazy.score >= 160u || (lazy.tries & 7u) == 0u) &&
+        if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u) &&
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
             first_tables<S>(idx1, c.rdepth0, cols, s0, L);
             r = step(e0, e3);
@@ -511,7 +583,7 @@ __device__ __forceinline__ bool light_block(
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
         if (r == 0) {
-            rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
+            if (!ONELINE) rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
             for (;;) {
                 if (!resume && (r = step(e0, e3)) != 0) break;
                 resume = false;
@@ -538,16 +610,16 @@ __device__ __forceinline__ bool light_block(
     return false;
 }
 
-template <int NK, bool ORDERED, typename S>
+template <int NK, bool ORDERED, typename S, bool ONELINE>
 __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (&hrow)[NK], uint32_t ordv,
                                           const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
                                           uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
                                           uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy,
-                                          LazyState& lazy)
+                                          LazyState& lazy, int32_t* j0_out)
 {
-    const bool left = light_block<NK, ORDERED, S>(x, hrow, c, cols, L, budget, split_steps, ordv,
-                                                  make_buf(cw + row, (uint32_t)c.n), queries + b, abandoned + b,
-                                                  lazy);
+    const bool left = light_block<NK, ORDERED, S, ONELINE>(x, hrow, c, cols, L, budget, split_steps, ordv,
+                                                           make_buf(cw + row, (uint32_t)c.n), queries + b,
+                                                           abandoned + b, lazy, j0_out ? j0_out + b : nullptr);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
         heavy[slot] = b;
@@ -614,13 +686,13 @@ struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; 
 template <int NKMAX, typename S>
 constexpr int light_waves() { return (NKMAX <= 4 && sizeof(S) == 4) ? 8 : 1; }
 
-template <int NKMAX, bool ORDERED, typename S, bool MIXED>
+template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE>
 __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(light_waves<NKMAX, S>())))
 light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
              const float* __restrict__ llr, int64_t nblocks, uint32_t budget, uint32_t split_steps,
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
-             int chunk)
+             int chunk, int32_t* __restrict__ j0_out)
 {
     // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
     // m x nk words), then their columns (sum of n entries)
@@ -724,7 +796,9 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                     }
                     bool yb[NKMAX];
                     const S s0 = hard_decision<NKMAX, S>(xs[kk], c.n, hr, yb);
-                    const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u);
+                    // (1-line offsets asked for: every block is ranked in phase 2)
+                    const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u) &&
+                                      !(ONELINE && j0_out != nullptr);
                     if (done) {
                         const buf_t cwr = make_buf(cw + rows[kk], (uint32_t)c.n);
 #pragma unroll
@@ -756,24 +830,26 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         const CodeDesc& c = codes.c[MIXED ? f.ci : 0];
         const S* cols = s_cols + (MIXED ? c.col_base : 0);
         if (HOIST) {
-            light_one<NKMAX, ORDERED, S>(f.x, hrow0, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw,
-                                         queries, abandoned, ctrs, heavy, lazy);
+            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hrow0, f.ordv, c, cols, L, b, f.row, budget, split_steps,
+                                                  cw, queries, abandoned, ctrs, heavy, lazy, j0_out);
         } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
             uint64_t hr[NKMAX];
             load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);
-            light_one<NKMAX, ORDERED, S>(f.x, hr, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw, queries,
-                                         abandoned, ctrs, heavy, lazy);
+            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hr, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw,
+                                                  queries, abandoned, ctrs, heavy, lazy, j0_out);
         } else if (c.nk == 1) {
             uint64_t hr[1];
             load_hrows<1>(s_rows + c.row_base, c.m, hr);
-            light_one<1, ORDERED, S>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, b, f.row,
-                                     budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy);
+            light_one<1, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, b,
+                                              f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy,
+                                              j0_out);
         } else {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
             uint64_t hr[K2];
             load_hrows<K2>(s_rows + c.row_base, c.m, hr);
-            light_one<K2, ORDERED, S>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L, b,
-                                      f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy);
+            light_one<K2, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L,
+                                               b, f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy,
+                                               lazy, j0_out);
         }
     };
 
@@ -801,11 +877,12 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
 
 // Heavy pass, one block shared by the workgroup's G waves (all waves call it).
 // Plain order only: blocks reach it after at least 64 steps or were never reordered.
-template <int NK, typename S, int G>
+// ONELINE: wave 0 fits the block's offset again and shares it through *s_j0.
+template <int NK, typename S, int G, bool ONELINE>
 __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __restrict__ llr_row, S* s_cols,
-                                            BlockLds<S>& L, uint32_t* best, uint32_t budget, uint32_t split_steps,
-                                            uint8_t* __restrict__ cw_row, uint64_t* __restrict__ q_out,
-                                            uint8_t* __restrict__ ab_out)
+                                            BlockLds<S>& L, uint32_t* best, int* s_j0, uint32_t budget,
+                                            uint32_t split_steps, uint8_t* __restrict__ cw_row,
+                                            uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
 {
     const int lane = lane_id();
     const int wave = threadIdx.x / ORBG_WAVE;
@@ -820,10 +897,11 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
         uint64_t hr[NK];
         load_hrows<NK>(c.rows, c.m, hr);
         const S s0 = hard_decision<NK, S>(x, n, hr, ybit);
-        rank_and_tables<NK, S>(x, n, s_cols, s0, c.rdepth, L);
+        const int j0 = rank_and_tables<NK, S, ONELINE>(x, n, s_cols, s0, c.rdepth, L);
+        if (ONELINE && lane == 0) *s_j0 = j0;
     }
     __syncthreads();
-    const uint2* __restrict__ sched = c.sched;
+    const uint2* __restrict__ sched = ONELINE ? oneline_schedule(c, (int)uniform_u32((uint32_t)*s_j0)) : c.sched;
     const uint32_t slen = c.slen;
     // wave w takes steps split + w, split + w + G, ...; the next one's entries
     // are loaded while the current one is tested
@@ -872,7 +950,7 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
     __syncthreads();
 }
 
-template <int NKMAX, typename S, bool MIXED, int G>
+template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
 __global__ void __launch_bounds__(G * ORBG_WAVE)
 heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
              const float* __restrict__ llr, uint32_t budget, uint32_t split_steps,
@@ -882,6 +960,7 @@ heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     __shared__ S s_cols[ORBG_WAVE * NKMAX];
     __shared__ BlockLds<S> L;
     __shared__ uint32_t best;
+    __shared__ int s_j0;
     __shared__ int64_t cur;
     const unsigned long long count = *(volatile unsigned long long*)(ctrs + ORBG_CTR_HEAVY_COUNT);
     for (;;) {
@@ -898,18 +977,18 @@ heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         const CodeDesc& c = codes.c[ci];
         const int64_t row = MIXED ? uniform_i64(row_off[b]) : b * c.n;
         if (c.nk == 1 || NKMAX == 1) {
-            heavy_block<1, S, G>(c, llr + row, s_cols, L, &best, budget, split_steps, cw + row, queries + b,
+            heavy_block<1, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
                                  abandoned + b);
         } else if (c.nk == 2 || NKMAX == 2) {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
-            heavy_block<K2, S, G>(c, llr + row, s_cols, L, &best, budget, split_steps, cw + row, queries + b,
+            heavy_block<K2, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
                                   abandoned + b);
         } else if (c.nk == 4 || NKMAX == 4) {
             constexpr int K4 = NKMAX >= 4 ? 4 : 1;
-            heavy_block<K4, S, G>(c, llr + row, s_cols, L, &best, budget, split_steps, cw + row, queries + b,
+            heavy_block<K4, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
                                   abandoned + b);
         } else {
-            heavy_block<NKMAX, S, G>(c, llr + row, s_cols, L, &best, budget, split_steps, cw + row, queries + b,
+            heavy_block<NKMAX, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
                                      abandoned + b);
         }
     }
@@ -920,7 +999,7 @@ __global__ void reset_counters_kernel(unsigned long long* c)
     for (int i = threadIdx.x; i < ORBG_CTR_WORDS; i += blockDim.x) c[i] = 0ull;
 }
 
-template <int NKMAX, bool ORDERED, typename S, bool MIXED>
+template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE>
 static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t split, hipStream_t stream)
 {
     uint32_t ncols = 0;
@@ -929,20 +1008,20 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
         ncols = e > ncols ? e : ncols;
     }
     const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
-    light_kernel<NKMAX, ORDERED, S, MIXED><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
+    light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
-        a.abandoned, a.ctrs, a.heavy, chunk);
+        a.abandoned, a.ctrs, a.heavy, chunk, a.j0);
 }
 
-template <int NKMAX, typename S, bool MIXED, int G>
+template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
 static void launch_heavy_g(const DecodeArgs& a, uint32_t split, hipStream_t stream)
 {
     const int64_t wgs = (int64_t)a.cus * (a.p.heavy_wg_per_cu > 0 ? a.p.heavy_wg_per_cu : 2);
-    heavy_kernel<NKMAX, S, MIXED, G><<<(unsigned)wgs, G * ORBG_WAVE, 0, stream>>>(
+    heavy_kernel<NKMAX, S, MIXED, G, ONELINE><<<(unsigned)wgs, G * ORBG_WAVE, 0, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.budget, split, a.cw, a.queries, a.abandoned, a.ctrs, a.heavy);
 }
 
-template <int NKMAX, bool ORDERED, typename S, bool MIXED>
+template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE = false>
 static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
 {
     int64_t wgs = a.nblocks;
@@ -958,11 +1037,11 @@ static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
     chunk = chunk > 64 ? 64 : chunk;                    // a chunk's blocks fit one 64-bit mask
     const uint32_t split = (a.heavy != nullptr && a.p.split_steps > 0) ? (uint32_t)a.p.split_steps : 0u;
     reset_counters_kernel<<<1, 64, 0, stream>>>(a.ctrs);
-    launch_light<NKMAX, ORDERED, S, MIXED>(a, wgs, chunk, split, stream);
+    launch_light<NKMAX, ORDERED, S, MIXED, ONELINE>(a, wgs, chunk, split, stream);
     if (split) {
-        if (a.p.heavy_waves >= 16) launch_heavy_g<NKMAX, S, MIXED, 16>(a, split, stream);
-        else if (a.p.heavy_waves >= 8) launch_heavy_g<NKMAX, S, MIXED, 8>(a, split, stream);
-        else launch_heavy_g<NKMAX, S, MIXED, 4>(a, split, stream);
+        if (a.p.heavy_waves >= 16) launch_heavy_g<NKMAX, S, MIXED, 16, ONELINE>(a, split, stream);
+        else if (a.p.heavy_waves >= 8) launch_heavy_g<NKMAX, S, MIXED, 8, ONELINE>(a, split, stream);
+        else launch_heavy_g<NKMAX, S, MIXED, 4, ONELINE>(a, split, stream);
     }
     return hipGetLastError();
 }
@@ -978,6 +1057,13 @@ static hipError_t launch_nk(const DecodeArgs& a, bool s32, hipStream_t stream)
     return launch_all<NKMAX, false, uint64_t, MIXED>(a, stream);
 }
 
+template <int NKMAX>
+static hipError_t launch_oneline(const DecodeArgs& a, bool s32, hipStream_t stream)
+{
+    if (s32) return launch_all<NKMAX, false, uint32_t, false, true>(a, stream);
+    return launch_all<NKMAX, false, uint64_t, false, true>(a, stream);
+}
+
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream)
 {
     if (a.nblocks < 1) return hipSuccess;
@@ -987,6 +1073,14 @@ hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream)
         mmax = a.codes.c[i].m > mmax ? a.codes.c[i].m : mmax;
     }
     const bool s32 = mmax <= 32;
+    if (a.oneline) {                                    // one code, plain batch order
+        if (a.mixed || a.order) return hipErrorInvalidValue;
+        if (nk <= 1) return launch_oneline<1>(a, s32, stream);
+        if (nk <= 2) return launch_oneline<2>(a, s32, stream);
+        if (nk <= 4) return launch_oneline<4>(a, s32, stream);
+        if (nk <= 8) return launch_oneline<8>(a, s32, stream);
+        return launch_oneline<16>(a, s32, stream);
+    }
     if (a.mixed) {
         if (nk <= 1) return launch_nk<1, true>(a, s32, stream);
         if (nk <= 2) return launch_nk<2, true>(a, s32, stream);

@@ -38,7 +38,23 @@ struct Schedule {
     int wlast;          // logistic weight of the last entry
 };
 
+// 1-line ORBGRAND schedules for one (n, len): j0max + 2 schedules of `len`
+// entries (same packing), the one for offset J0 at entries + (J0 + 1) * stride,
+// J0 = -1 .. j0max; fitted offsets above j0max use the last one.
+struct Schedule1 {
+    int n;
+    uint64_t len;
+    uint64_t nbatch;    // batches of 64 per schedule
+    uint64_t stride;    // entries per schedule including ORBG_SCHED_PAD zero batches
+    int j0max;
+    uint2* entries;
+    int rmax;           // largest rank any schedule references
+};
+
 int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, char* err, size_t errlen);
+int orbg_build_schedule_1line(int n, uint64_t len, hipStream_t stream, Schedule1* out, char* err, size_t errlen);
+// Unpacks `count` entries from `entries` to 16-byte lists of 1-based ranks.
+int orbg_unpack_entries(const uint2* entries, uint64_t count, uint8_t* d_out, hipStream_t stream);
 // Unpacks the first `count` entries to 16-byte lists of 1-based ranks.
 int orbg_unpack_schedule(const Schedule* s, uint64_t count, uint8_t* d_out, hipStream_t stream);
 

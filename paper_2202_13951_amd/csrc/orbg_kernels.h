@@ -20,7 +20,9 @@ struct CodeDesc {
     uint32_t row_base;         // first word of this code's rows in the launch's LDS row table
     const uint64_t* cols;      // n packed parity-check columns
     const uint64_t* rows;      // m x nk packed parity-check rows (bit l of word j = H[r][64 j + l])
-    const uint2* sched;        // schedule entries for this n
+    const uint2* sched;        // schedule entries for this n (1-line: the schedule of offset -1)
+    int j0max;                 // 1-line: largest offset with a schedule of its own
+    uint32_t sstride;          // 1-line: entries between the schedules of consecutive offsets
 };
 
 struct CodeTable {
@@ -47,6 +49,8 @@ struct DecodeArgs {
     int64_t nblocks;
     uint32_t budget;
     const uint8_t* order;      // device, nblocks x 64, or nullptr for plain order
+    bool oneline;              // 1-line ORBGRAND order (one code, plain batch order)
+    int32_t* j0;               // device, nblocks 1-line offsets, or nullptr
     uint8_t* cw;
     uint64_t* queries;
     uint8_t* abandoned;

@@ -25,13 +25,17 @@
 #include "orbg_device.h"
 #include "orbg_internal.h"
 
+#include <algorithm>
+#include <stdint.h>
+#include <vector>
+
 namespace orbg {
 
-// counts layout: [ORBG_WMAX_H + 1][ORBG_WCAP + 1]
-__global__ void __launch_bounds__(ORBG_WCAP + 1)
-class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int* wlast_out)
+// N[w][W] = number of w-subsets of {1..n} with sum W (w <= ORBG_WMAX_H,
+// W <= ORBG_WCAP): the 0/1 knapsack recursion over the values v = 1..n, one
+// thread per W.  Called by all ORBG_WCAP + 1 threads of the block.
+__device__ void subset_counts(int n, uint64_t (*N)[ORBG_WCAP + 1])
 {
-    __shared__ uint64_t N[ORBG_WMAX_H + 1][ORBG_WCAP + 1];
     const int W = threadIdx.x;
 #pragma unroll
     for (int w = 0; w <= ORBG_WMAX_H; ++w) N[w][W] = (w == 0 && W == 0) ? 1ull : 0ull;
@@ -45,6 +49,15 @@ class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int
             __syncthreads();
         }
     }
+}
+
+// counts layout: [ORBG_WMAX_H + 1][ORBG_WCAP + 1]
+__global__ void __launch_bounds__(ORBG_WCAP + 1)
+class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int* wlast_out)
+{
+    __shared__ uint64_t N[ORBG_WMAX_H + 1][ORBG_WCAP + 1];
+    subset_counts(n, N);
+    const int W = threadIdx.x;
     if (W != 0) return;
     // lay the classes out: W ascending, w ascending, until len entries exist
     uint64_t off = 0;
@@ -240,6 +253,164 @@ int orbg_unpack_schedule(const Schedule* s, uint64_t count, uint8_t* d_out, hipS
 {
     if (count > s->len) return -1;
     unpack_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(s->entries, count, d_out);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// ---------------------------------------------------------------------------
+// 1-line ORBGRAND schedules.  With one segment of slope beta = 1 and offset J0
+// (Sec. IV, eqs. (relest_seg) and (quant) with m = 1), the reliability weight
+// of a pattern of Hamming weight w and logistic weight W is J0 w + W
+// (eq. (W2IJ)), so the 1-line order takes the same (W, w) classes as the basic
+// order, each still in Landslide (lexicographic) order, but sorted by
+// (J0 w + W, w).  One schedule per J0 in [-1, j0max] is built, J0 = -1 first,
+// each `stride` entries apart.
+//
+// j0max: for J0 at least the largest W among the first len patterns of the
+// order that takes Hamming weight first (then W, then lexicographic order),
+// every J0 gives that same prefix (a pattern p of that prefix and any pattern q
+// of larger Hamming weight satisfy J0 (w_q - w_p) + W_q - W_p > 0), so larger
+// fitted values decode with the schedule of j0max.
+
+__global__ void __launch_bounds__(ORBG_WCAP + 1) subset_count_kernel(int n, uint64_t* out)
+{
+    __shared__ uint64_t N[ORBG_WMAX_H + 1][ORBG_WCAP + 1];
+    subset_counts(n, N);
+    for (int w = 0; w <= ORBG_WMAX_H; ++w) out[w * (ORBG_WCAP + 1) + threadIdx.x] = N[w][threadIdx.x];
+}
+
+static int64_t host_max_sum(int w, int n) { return (int64_t)w * n - (int64_t)w * (w - 1) / 2; }
+
+// Class layout of every J0 schedule from the subset counts N (host side).
+static int layout_1line(int n, uint64_t len, uint64_t stride, const uint64_t* N, std::vector<ClassInfo>& out,
+                        int* j0max, char* err, size_t errlen)
+{
+    auto cnt = [&](int w, int W) { return N[w * (ORBG_WCAP + 1) + W]; };
+    const int wtop = n < ORBG_WMAX_H ? n : ORBG_WMAX_H;
+    // largest W of the first len patterns in Hamming-weight-first order
+    uint64_t off = 0;
+    int wmaxW = 0;
+    for (int w = 0; w <= wtop && off < len; ++w) {
+        for (int W = 0; W <= ORBG_WCAP && off < len; ++W)
+            if (cnt(w, W)) { off += cnt(w, W); wmaxW = W > wmaxW ? W : wmaxW; }
+        if (off < len && host_max_sum(w, n) > ORBG_WCAP) {
+            snprintf(err, errlen, "1-line schedule: %llu patterns of Hamming weight <= %d need logistic weights "
+                     "above %d", (unsigned long long)len, w, ORBG_WCAP);
+            return -1;
+        }
+    }
+    if (off < len) {
+        snprintf(err, errlen, "1-line schedule: %llu patterns need Hamming weights above %d",
+                 (unsigned long long)len, ORBG_WMAX_H);
+        return -1;
+    }
+    *j0max = wmaxW;
+    struct Cls { int64_t cost; int w; int W; };
+    std::vector<Cls> cls;
+    for (int J = -1; J <= wmaxW; ++J) {
+        cls.clear();
+        for (int w = 0; w <= wtop; ++w)
+            for (int W = 0; W <= ORBG_WCAP; ++W)
+                if (cnt(w, W)) cls.push_back({(int64_t)J * w + W, w, W});
+        std::sort(cls.begin(), cls.end(), [](const Cls& a, const Cls& b) {
+            return a.cost != b.cost ? a.cost < b.cost : a.w < b.w;
+        });
+        // the cheapest class the counts do not hold (W > WCAP or w > WMAX_H)
+        int64_t missing = INT64_MAX;
+        for (int w = 1; w <= n; ++w) {
+            const int64_t lo = (int64_t)w * (w + 1) / 2;
+            int64_t W0 = -1;
+            if (w > ORBG_WMAX_H) W0 = lo;
+            else if (host_max_sum(w, n) > ORBG_WCAP) W0 = lo > ORBG_WCAP + 1 ? lo : ORBG_WCAP + 1;
+            if (W0 >= 0 && (int64_t)J * w + W0 < missing) missing = (int64_t)J * w + W0;
+        }
+        const uint64_t base = (uint64_t)(J + 1) * stride;
+        uint64_t o = 0;
+        int64_t last = 0;
+        for (const Cls& c : cls) {
+            if (o >= len) break;
+            if (c.w > ORBG_HIGH_SLOTS && c.W > ORBG_WLEVEL_PACKED) {
+                snprintf(err, errlen, "1-line schedule (J0 = %d): class W = %d, w = %d does not fit an entry", J, c.W,
+                         c.w);
+                return -1;
+            }
+            const uint64_t take = cnt(c.w, c.W) < len - o ? cnt(c.w, c.W) : len - o;
+            out.push_back({c.W, c.w, base + o, take});
+            o += take;
+            last = c.cost;
+        }
+        if (o < len || last >= missing) {
+            snprintf(err, errlen, "1-line schedule (J0 = %d): %llu patterns reach logistic weights above %d", J,
+                     (unsigned long long)len, ORBG_WCAP);
+            return -1;
+        }
+    }
+    return 0;
+}
+
+int orbg_build_schedule_1line(int n, uint64_t len, hipStream_t stream, Schedule1* out, char* err, size_t errlen)
+{
+    const int WN = (ORBG_WMAX_H + 1) * (ORBG_WCAP + 1);
+    uint64_t* d_counts = nullptr;
+    int* d_small = nullptr;
+    if (hipMalloc(&d_counts, sizeof(uint64_t) * WN) != hipSuccess || hipMalloc(&d_small, sizeof(int) * 4) != hipSuccess) {
+        snprintf(err, errlen, "1-line schedule: device allocation failed");
+        (void)hipFree(d_counts); (void)hipFree(d_small);
+        return -2;
+    }
+    std::vector<uint64_t> N(WN);
+    subset_count_kernel<<<1, ORBG_WCAP + 1, 0, stream>>>(n, d_counts);
+    (void)hipMemcpyAsync(N.data(), d_counts, sizeof(uint64_t) * WN, hipMemcpyDeviceToHost, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        snprintf(err, errlen, "1-line schedule: count kernel failed: %s", hipGetErrorString(hipGetLastError()));
+        (void)hipFree(d_counts); (void)hipFree(d_small);
+        return -3;
+    }
+    (void)hipFree(d_counts);
+    const uint64_t nbatch = (len + 63) / 64;
+    const uint64_t stride = (nbatch + ORBG_SCHED_PAD) * 64;
+    std::vector<ClassInfo> classes;
+    int j0max = 0;
+    int rc = layout_1line(n, len, stride, N.data(), classes, &j0max, err, errlen);
+    if (rc != 0) { (void)hipFree(d_small); return rc; }
+    const uint64_t total = (uint64_t)(j0max + 2) * stride;
+    ClassInfo* d_classes = nullptr;
+    uint2* d_entries = nullptr;
+    if (hipMalloc(&d_classes, sizeof(ClassInfo) * classes.size()) != hipSuccess ||
+        hipMalloc(&d_entries, sizeof(uint2) * total) != hipSuccess) {
+        snprintf(err, errlen, "1-line schedule: cannot allocate %d schedules of %llu entries", j0max + 2,
+                 (unsigned long long)stride);
+        (void)hipFree(d_classes); (void)hipFree(d_entries); (void)hipFree(d_small);
+        return -2;
+    }
+    (void)hipMemcpyAsync(d_classes, classes.data(), sizeof(ClassInfo) * classes.size(), hipMemcpyHostToDevice, stream);
+    (void)hipMemsetAsync(d_small, 0, sizeof(int) * 4, stream);
+    (void)hipMemsetAsync(d_entries, 0, sizeof(uint2) * total, stream);
+    const int nclass = (int)classes.size();
+    class_fill_kernel<<<(nclass + 63) / 64, 64, 0, stream>>>(n, total, d_classes, nclass, d_entries);
+    rank_depth_kernel<<<(unsigned)((total / 64 + 255) / 256), 256, 0, stream>>>(d_entries, total, total / 64,
+                                                                                 d_small);
+    int rmax[2] = {0, 0};
+    (void)hipMemcpyAsync(rmax, d_small, sizeof(int) * 2, hipMemcpyDeviceToHost, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        snprintf(err, errlen, "1-line schedule: fill kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        (void)hipFree(d_classes); (void)hipFree(d_entries); (void)hipFree(d_small);
+        return -3;
+    }
+    (void)hipFree(d_classes);
+    (void)hipFree(d_small);
+    out->n = n;
+    out->len = len;
+    out->nbatch = nbatch;
+    out->stride = stride;
+    out->j0max = j0max;
+    out->entries = d_entries;
+    out->rmax = rmax[0];
+    return 0;
+}
+
+int orbg_unpack_entries(const uint2* entries, uint64_t count, uint8_t* d_out, hipStream_t stream)
+{
+    unpack_kernel<<<(unsigned)((count + 255) / 256), 256, 0, stream>>>(entries, count, d_out);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
