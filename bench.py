@@ -5,7 +5,8 @@ Eb/N0 = 4.0, 4.5, ..., 7.0 dB, 10^6 blocks per point, query budget 10^5, plain
 ORBGRAND.  One step decodes all 7 x 10^6 blocks (LLRs already resident in HBM)
 with one decode call (light pass + heavy pass).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bch127|rlc32|mixed|learned|stream]
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+                  [--workload bch127|bch127_1line|rlc32|mixed|learned|stream]
 
 --workload mixed: random linear codes (64,52), (128,116), (256,240) mixed 1:2:1
 in one persistent launch per Eb/N0 point (3..6 dB, 4x10^6 blocks, budget
@@ -13,6 +14,8 @@ in one persistent launch per Eb/N0 point (3..6 dB, 4x10^6 blocks, budget
 heavy pass.
 --workload learned: the learned batch-order proposal on RLC(128,105), trained
 on the GPU, against plain ORBGRAND on the same held-out blocks.
+--workload bch127_1line: the default workload decoded by 1-line ORBGRAND (the
+one-segment fit of Sec. IV), with basic ORBGRAND on the same blocks per point.
 --workload stream: Poisson request arrivals (single blocks of four codes) served
 by a host loop of mixed-code launches; p50/p99 latency and blocks/s at 1e5 and
 1e6 requests/s.
@@ -44,6 +47,11 @@ WORKLOADS = {
                    blocks=10 ** 6, budget=10 ** 5,
                    desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
                         "budget 1e5, plain ORBGRAND"),
+    "bch127_1line": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
+                         blocks=10 ** 6, budget=10 ** 5, oneline=True, tuned_as="bch127",
+                         desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
+                              "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. IV) against basic ORBGRAND "
+                              "on the same blocks"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
     "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),
@@ -138,24 +146,26 @@ def profiled_traffic(workload: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0):
+def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0, oneline=False):
     """Times the oracle (as it stands) on the first blocks of every Eb/N0 point.
     rows(p, count) -> host float32 [count, n], the first `count` rows of point p.
     A first pass on 2000 blocks per point sizes the sample (that pass overstates the
-    per-block cost, so the timed sample lasts about half of target_s)."""
+    per-block cost, so the timed sample lasts about half of target_s).  oneline: the
+    oracle's 1-line decoder."""
     from oracle import oracle as O
+    dec = O.decode_1line if oneline else O.decode
     threads = len(os.sched_getaffinity(0))
     per = min(2000, per_max)
     xs = [rows(p, per) for p in range(npoints)]
     t0 = time.perf_counter()
     for x in xs:
-        O.decode(H, x, budget, threads)
+        dec(H, x, budget, threads)
     dt = time.perf_counter() - t0
     per = int(min(per_max, max(per, per * target_s / max(dt, 1e-3))))
     xs = [rows(p, per) for p in range(npoints)]
     t0 = time.perf_counter()
     for x in xs:
-        O.decode(H, x, budget, threads)
+        dec(H, x, budget, threads)
     dt = time.perf_counter() - t0
     nb = per * npoints
     return {"value": nb / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
@@ -313,6 +323,130 @@ def run_single(args, wl, dev):
         del src, dst
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(H, lambda p, c: llr[p * B:p * B + c].cpu().numpy(), P, B, budget)
+    return result
+
+
+def run_oneline(args, wl, dev):
+    """1-line ORBGRAND over all points in one call per step (timed), then per point:
+    BLER, queries and the fitted offsets of the 1-line decoder, and the basic decoder
+    on the same blocks, each timed on its own."""
+    import torch
+    from paper_2202_13951_amd import binding
+    H, llr, sent = single_inputs(wl, dev)
+    n, budget = wl["n"], wl["budget"]
+    P, B = len(wl["ebn0"]), wl["blocks"]
+    params, knobs = tuned_params(wl.get("tuned_as", args.workload), not args.no_tuned)
+    cw = torch.empty_like(sent)
+    q = torch.empty((P * B,), dtype=torch.int64, device=dev)
+    ab = torch.empty((P * B,), dtype=torch.uint8, device=dev)
+    out = (cw, q, ab)
+    stream = torch.cuda.current_stream()
+
+    def one():
+        binding.orbg_decode_1line(H, llr, budget, j0=False, params=params, out=out)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        one()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        one()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    blocks = P * B
+    # the fitted offsets of every block (an untimed call that also ranks the blocks
+    # whose hard decision is a codeword), and the same results
+    j0 = torch.empty((P * B,), dtype=torch.int32, device=dev)
+    cw2, q2, ab2, _ = binding.orbg_decode_1line(H, llr, budget, j0=j0, params=params)
+    torch.cuda.synchronize()
+    same = bool((cw2 == cw).all().item() and (q2 == q).all().item() and (ab2 == ab).all().item())
+    del cw2, q2, ab2
+    q_np = q.cpu().numpy()
+    ab_np = ab.cpu().numpy()
+    j0_np = j0.cpu().numpy()
+    err = (cw != sent).any(dim=1).cpu().numpy()
+    _, j0max = binding.orbg_schedule_export_1line(n, budget, 0, 0)
+
+    bcw = torch.empty((B, n), dtype=torch.uint8, device=dev)
+    bq = torch.empty((B,), dtype=torch.int64, device=dev)
+    bab = torch.empty((B,), dtype=torch.uint8, device=dev)
+    binding.orbg_decode_ex(H, llr[:B], budget, params=params, out=(bcw, bq, bab))   # builds its schedule
+    torch.cuda.synchronize()
+    per_point = {}
+    for p, e in enumerate(wl["ebn0"]):
+        sl = slice(p * B, (p + 1) * B)
+        ne = int(err[sl].sum())
+        jp = j0_np[sl]
+        vals, cnts = np.unique(np.clip(jp, -1, 9), return_counts=True)
+        pt = {"bler": ne / B, "errors": ne, "bler_ci95": list(wilson(ne, B)),
+              "mean_queries": float(q_np[sl].mean()), "abandoned": int(ab_np[sl].sum()),
+              "breakdown": query_breakdown(q_np[sl], ab_np[sl], err[sl], budget),
+              "j0": {"mean": float(jp.mean()), "min": int(jp.min()), "max": int(jp.max()),
+                     "share": {("9+" if v == 9 else str(int(v))): float(c / B) for v, c in zip(vals, cnts)},
+                     "above_j0max": float((jp > j0max).mean())}}
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        binding.orbg_decode_1line(H, llr[sl], budget, j0=False, params=params, out=(cw[sl], q[sl], ab[sl]))
+        b_.record(stream)
+        torch.cuda.synchronize()
+        t = a_.elapsed_time(b_) / 1e3
+        pt["blocks_per_s"] = B / t
+        pt["queries_per_s"] = float(q_np[sl].sum()) / t
+        a_.record(stream)
+        binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=(bcw, bq, bab))
+        b_.record(stream)
+        torch.cuda.synchronize()
+        tb = a_.elapsed_time(b_) / 1e3
+        berr = (bcw != sent[sl]).any(dim=1).cpu().numpy()
+        bq_np = bq.cpu().numpy()
+        nb = int(berr.sum())
+        pt["basic"] = {"bler": nb / B, "errors": nb, "bler_ci95": list(wilson(nb, B)),
+                       "mean_queries": float(bq_np.mean()), "abandoned": int(bab.sum().item()),
+                       "blocks_per_s": B / tb}
+        # blocks one decoder gets right and the other wrong
+        pt["only_1line_correct"] = int((~err[sl] & berr).sum())
+        pt["only_basic_correct"] = int((err[sl] & ~berr).sum())
+        per_point[f"{e:.1f}"] = pt
+
+    kavg = float(np.mean(kern_ms)) / 1e3
+    q_sum = int(q_np.sum())
+    n_sorted = int((q_np > 1).sum())
+    ops = algorithmic_ops(q_sum, n_sorted, n)
+    hbm_bytes = blocks * (4 * n + n + 8 + 1)
+    result = {
+        "metric": METRIC,
+        "value": blocks / (wall / args.steps),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "code": wl["code"], "n": n, "k": wl["k"], "ebn0_db": wl["ebn0"],
+                   "blocks_per_step": blocks, "budget": budget, "j0max": j0max},
+        "queries_per_s": q_sum / (wall / args.steps),
+        "mean_queries": q_sum / blocks,
+        "kernel_ms": float(np.mean(kern_ms)),
+        "launch_params": knobs if knobs else "library defaults",
+        "offsets_call_identical": same,
+        "per_point": per_point,
+        "roofline": {"bound": "alu", "achieved": ops / kavg / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS, "traffic": None,
+                     "kernel": "light_kernel + heavy_kernel, 1-line (one decode call)", "ops_per_launch": ops,
+                     "hbm": {"achieved_GBps": hbm_bytes / kavg / 1e9, "peak_GBps": PEAK_HBM / 1e9,
+                             "frac": hbm_bytes / kavg / PEAK_HBM, "bytes_per_launch": hbm_bytes}},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(H, lambda p, c: llr[p * B:p * B + c].cpu().numpy(), P, B, budget,
+                                              oneline=True)
     return result
 
 
@@ -633,6 +767,8 @@ def main():
         result = run_mixed(args, wl, dev)
     elif "train_pairs" in wl:
         result = run_learned(args, wl, dev)
+    elif wl.get("oneline"):
+        result = run_oneline(args, wl, dev)
     else:
         result = run_single(args, wl, dev)
     if args.ebn0 and "roofline" in result:

@@ -506,10 +506,38 @@ __device__ __forceinline__ bool light_block(
     uint32_t q = budget;
     uint32_t win_lo = 0, win_hi = 0;     // winning entry (wave-uniform)
 
-    // 1-line: the offset needs the whole ranking, made here when the block needs
-    // a search or its offset is asked for
+    // 1-line: patterns 2 and 3 are {1} and {2} whatever the offset (J0 w + W
+    // orders them right after the empty pattern for every J0 >= -1), so they are
+    // tested on ranks 1 and 2 alone, found without sorting the block; the same
+    // per-wave score as the basic first-batch ranking (here: how often one of
+    // them decides) turns the attempt off while it rarely pays.  Not when the
+    // offsets are asked for.
     const uint2* __restrict__ sched = c.sched;
-    if (ONELINE && (s0 != 0 || j0_out != nullptr)) {
+    bool early = false;
+    if (ONELINE && s0 != 0 && j0_out == nullptr && n >= 2 && budget >= 3u) {
+        lazy.tries = uniform_u32(lazy.tries + 1u);
+        uint32_t idx1 = 0;
+        if ((lazy.score >= 96u || (lazy.tries & 7u) == 0u) && rank_first<NK, S>(x, n, 2, lazy.tau, L, idx1)) {
+            const uint32_t i1 = uniform_u32((uint32_t)__builtin_amdgcn_readlane((int)idx1, 0));
+            const uint32_t i2 = uniform_u32((uint32_t)__builtin_amdgcn_readlane((int)idx1, 1));
+            const S h1 = cols[i1], h2 = cols[i2];
+            if (s0 == h1 || s0 == h2) {
+                early = true;
+                found = true;
+                q = s0 == h1 ? 2u : 3u;
+                win_lo = s0 == h1 ? 1u : 2u;          // mask of ranks 1..8: rank 1 or rank 2
+                if (lane == 0) {
+                    L.pi[1] = (uint16_t)i1;
+                    L.pi[2] = (uint16_t)i2;
+                }
+                wave_lds_sync();
+            }
+            lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (early ? 32u : 0u));
+        }
+    }
+    // otherwise the offset needs the whole ranking, made here when the block
+    // needs a search or its offset is asked for
+    if (ONELINE && !early && (s0 != 0 || j0_out != nullptr)) {
         const int j0 = rank_and_tables<NK, S, true>(x, n, cols, s0, c.rdepth, L);
         if (j0_out != nullptr) write_offset(j0_out, j0);
         sched = oneline_schedule(c, j0);
@@ -517,7 +545,9 @@ __device__ __forceinline__ bool light_block(
 
     // s0 == 0: the empty pattern (entry 0 of batch 0) is a member; it is the first
     // hit when batch 0 is tested first (always in the plain and 1-line orders)
-    if (s0 == 0 && (!ORDERED || batch_at<ORDERED>(ordv, 0) == 0)) {
+    if (early) {
+        // decided by {1} or {2}
+    } else if (s0 == 0 && (!ORDERED || batch_at<ORDERED>(ordv, 0) == 0)) {
         found = true;
         q = 1;
     } else {

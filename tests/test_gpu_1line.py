@@ -89,7 +89,9 @@ def test_launch_shapes(gpu_device, params):
     H, G = codes.code("bch127_113")
     llr, _ = channel.awgn_llr(G, 1500, 4.0, seed=77)
     want = O.decode_1line(H, llr, 10 ** 5, THREADS)
-    _assert_same(_gpu(H, llr, 10 ** 5, gpu_device, params=binding.LaunchParams(**params)), want, str(params))
+    p = binding.LaunchParams(**params)
+    _assert_same(_gpu(H, llr, 10 ** 5, gpu_device, params=p), want, str(params))
+    _assert_same(_gpu(H, llr, 10 ** 5, gpu_device, params=p, j0=None), want, f"{params} no j0", check_j0=False)
 
 
 @pytest.mark.parametrize("n,k,budget,ebn0", [(8, 3, 2 ** 8, 1.0), (12, 5, 2 ** 12, 1.5), (63, 50, 20000, 2.5),
@@ -103,7 +105,9 @@ def test_shapes_and_ragged_lengths(gpu_device, n, k, budget, ebn0):
     H = codes.rlc_H(n, k, seed=n * 5 + k)
     G = codes.generator_matrix(H)
     llr, _ = channel.awgn_llr(G, 300, ebn0, seed=n + 3 * k)
-    _assert_same(_gpu(H, llr, budget, gpu_device), O.decode_1line(H, llr, budget, THREADS), f"n={n}")
+    want = O.decode_1line(H, llr, budget, THREADS)
+    _assert_same(_gpu(H, llr, budget, gpu_device), want, f"n={n}")
+    _assert_same(_gpu(H, llr, budget, gpu_device, j0=None), want, f"n={n} no j0", check_j0=False)
 
 
 def test_special_values_and_fit_edges(gpu_device):
@@ -135,6 +139,7 @@ def test_special_values_and_fit_edges(gpu_device):
     want = O.decode_1line(H, llr, 5000, THREADS)
     assert want[3][16:40].max() > 300                         # above j0max (largest W of the prefix)
     _assert_same(_gpu(H, llr, 5000, gpu_device), want, "special")
+    _assert_same(_gpu(H, llr, 5000, gpu_device, j0=None), want, "special no j0", check_j0=False)
 
 
 def test_budget_edges(gpu_device):
@@ -145,6 +150,7 @@ def test_budget_edges(gpu_device):
     for budget in (1, 2, 63, 64, 65, 127, 4097, 30000):
         want = O.decode_1line(H, llr, budget, THREADS)
         _assert_same(_gpu(H, llr, budget, gpu_device), want, f"budget={budget}")
+        _assert_same(_gpu(H, llr, budget, gpu_device, j0=None), want, f"budget={budget} no j0", check_j0=False)
     assert want[2].sum() > 0
 
 
@@ -162,7 +168,8 @@ def test_empty_batch_and_unsupported(gpu_device):
 
 def test_bch_full_size_sampled(gpu_device):
     """BCH(127,113), 10^6 blocks at 5 dB, budget 10^5, one launch: sampled blocks
-    against the oracle, invariants on every block."""
+    against the oracle, invariants on every block; the launch without offsets
+    (patterns {1} and {2} tested before any sort) returns the same results."""
     print("1-line bch full size", flush=True)
     H, G = codes.code("bch127_113")
     N, budget = 10 ** 6, 10 ** 5
@@ -177,3 +184,5 @@ def test_bch_full_size_sampled(gpu_device):
     ok = torch.from_numpy(gab == 0).to(gpu_device)
     syn = (torch.from_numpy(gcw).to(gpu_device).float() @ Hf.T).remainder(2)
     assert not syn[ok].any()
+    ncw, nq, nab, _ = _gpu(H, llr, budget, gpu_device, j0=None)
+    assert (ncw == gcw).all() and (nq == gq).all() and (nab == gab).all()
