@@ -558,41 +558,52 @@ __device__ __forceinline__ bool light_block(
         // last one masks lanes.  Indices fit 32 bits.
         const uint32_t lim = min(budget, slen);
         const uint32_t T = (lim + ORBG_WAVE - 1) / ORBG_WAVE;
-        const uint64_t tail = low_lanes(lim - (T - 1) * ORBG_WAVE);
         // entries of step u: a schedule holds whole batches of 64 entries and
         // ORBG_SCHED_PAD zero batches after its last one, so the loads for up to
         // three steps past the end stay inside it and need no bounds check
         auto entries = [&](uint32_t u) -> uint2 {
-            return load_entry(sched + (size_t)batch_at<ORDERED>(ordv, u) * ORBG_WAVE, (uint32_t)lane);
+            return load_entry(sched, batch_at<ORDERED>(ordv, u) * ORBG_WAVE + (uint32_t)lane);
         };
         // the first three steps' entries do not depend on the block's order of
         // reliability: they load while the ranks are sorted (1-line: after the
         // ranking that picks the schedule)
         uint2 e0 = entries(0), e1 = entries(1), e2 = entries(2), e3 = make_uint2(0u, 0u);
         uint32_t t = 0;
-        // One step: load the entries of step t + 3, test those of step t.
-        // Returns 0 (go on), 1 (hit), 2 (no hit, nothing left), 3 (split point).
-        // Four register sets rotate, so a load is consumed three steps after it
-        // was issued.
         // the search stops at step tend: the end of the queries, or the split
         // point if that comes first
         const uint32_t tend = (split_steps != 0 && split_steps < T) ? split_steps : T;
-        auto step = [&](const uint2 cur, uint2& ahead) -> int {
+        // One step: load the entries of step t + 3, test those of step t, move
+        // to step t + 1.  The search state is t, the steps left before tend and
+        // the ballot of the last step's hits: true when the search stops (a hit,
+        // or step tend reached).  Four register sets rotate, so a load is
+        // consumed three steps after it was issued.
+        uint64_t hits = 0;
+        uint32_t rem = tend;
+        auto step = [&](const uint2 cur, uint2& ahead) -> bool {
             ahead = entries(t + 3);
-            const S syn = entry_syndrome<S>(L, cur);
-            uint64_t hits = ballot(syn == 0);
-            const bool end = t + 1 >= tend;
-            if (end && t + 1 >= T) hits &= tail;
-            if (hits) {
-                const int wl = __builtin_ctzll(hits);
-                q = t * ORBG_WAVE + wl + 1;
-                win_lo = __builtin_amdgcn_readlane(cur.x, wl);
-                win_hi = __builtin_amdgcn_readlane(cur.y, wl);
+            hits = ballot(entry_syndrome<S>(L, cur) == 0);
+            ++t;
+            --rem;
+            return hits != 0 || rem == 0;
+        };
+        // 0 (go on), 1 (hit), 2 (no hit within the budget), 3 (split point).
+        // Only the last step of the queries holds lanes past the budget (query
+        // numbers above lim): a first hit there means no hit within the budget,
+        // so no lane mask is carried from step to step.  The winning entry is
+        // read again (one scalar load) rather than kept from the step.
+        auto outcome = [&](bool stop) -> int {
+            if (!stop) return 0;
+            if (hits) {                               // found in step t - 1
+                const uint32_t wl = (uint32_t)__builtin_ctzll(hits);
+                q = (t - 1) * ORBG_WAVE + wl + 1;
+                if (q > lim) return 2;
+                const uint32_t* w =
+                    reinterpret_cast<const uint32_t*>(sched + batch_at<ORDERED>(ordv, t - 1) * ORBG_WAVE + wl);
+                win_lo = scalar_load(w, 0);
+                win_hi = scalar_load(w, 1);
                 return 1;
             }
-            ++t;
-            if (end) return t >= T ? 2 : 3;
-            return 0;
+            return t * ORBG_WAVE >= lim ? 2 : 3;
         };
         // Plain order: most blocks end in the first batch, which only reaches
         // ranks 1..rdepth0, so those ranks are found first (rank_first) and the
@@ -608,19 +619,20 @@ __device__ __forceinline__ bool light_block(
         if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u) &&
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
             first_tables<S>(idx1, c.rdepth0, cols, s0, L);
-            r = step(e0, e3);
+            r = outcome(step(e0, e3));
             resume = true;
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
         if (r == 0) {
             if (!ONELINE) rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
             for (;;) {
-                if (!resume && (r = step(e0, e3)) != 0) break;
+                if (!resume && step(e0, e3)) break;
                 resume = false;
-                if ((r = step(e1, e0)) != 0) break;
-                if ((r = step(e2, e1)) != 0) break;
-                if ((r = step(e3, e2)) != 0) break;
+                if (step(e1, e0)) break;
+                if (step(e2, e1)) break;
+                if (step(e3, e2)) break;
             }
+            r = outcome(true);
         }
         // the entries prefetched for steps that will not run are taken here, so
         // their registers are free when the next block's code reuses them (no
