@@ -119,3 +119,44 @@ def test_hip_graph_replay(gpu_device):
         assert (cw.cpu().numpy() == eager[0]).all(), rep
         assert (q.cpu().numpy().astype(np.uint64) == eager[1]).all(), rep
         assert (ab.cpu().numpy() == eager[2]).all(), rep
+
+
+def test_mixed_full_size_sampled(gpu_device):
+    """The benchmark's mixed shape at its hardest point: 4 x 10^6 blocks of
+    (64,52):(128,116):(256,240) = 1:2:1 at 3 dB, budget 10^6, one launch in the
+    tuned launch shape the benchmark times.  Sampled blocks of every code (among
+    them the 50 that needed most queries) against the oracle; on every block
+    1 <= q <= budget, abandoned blocks at q = budget, and returned words with a
+    zero syndrome."""
+    print("mixed full size", flush=True)
+    from paper_2202_13951_amd import autotune
+    HG = [codes.code(nm) for nm in NAMES]
+    N, budget = 4 * 10 ** 6, 10 ** 6
+    llr, _, bc, ro = mixed.mixed_llr_torch([G for _, G in HG], [1, 2, 1], N, 3.0, seed=2030, device=gpu_device)
+    ids = [binding.orbg_code_register(H) for H, _ in HG]
+    cw = torch.zeros(llr.numel(), dtype=torch.uint8, device=gpu_device)
+    q = torch.zeros(N, dtype=torch.int64, device=gpu_device)
+    ab = torch.zeros(N, dtype=torch.uint8, device=gpu_device)
+    params = binding.LaunchParams(**autotune.load_tuned("mixed"))
+    binding.orbg_decode_mixed(ids, bc, ro, llr, budget, cw, q, ab, params=params)
+    torch.cuda.synchronize()
+    qn, abn, bcn, ron = q.cpu().numpy().astype(np.uint64), ab.cpu().numpy(), bc.cpu().numpy(), ro.cpu().numpy()
+    assert ((qn >= 1) & (qn <= budget)).all() and (qn[abn == 1] == budget).all()
+    rng = np.random.default_rng(3)
+    for ci, (H, G) in enumerate(HG):
+        n = H.shape[1]
+        mine = np.nonzero(bcn == ci)[0]
+        idx = np.unique(np.concatenate([rng.choice(mine, 120, replace=False), mine[np.argsort(qn[mine])[-17:]]]))
+        pos = torch.from_numpy(ron[idx][:, None] + np.arange(n)[None, :]).to(gpu_device)
+        rows = llr[pos].cpu().numpy()
+        ocw, oq, oab = O.decode(H, rows, budget, THREADS)
+        assert (cw[pos].cpu().numpy() == ocw).all(), NAMES[ci]
+        assert (qn[idx] == oq).all() and (abn[idx] == oab).all(), NAMES[ci]
+        # every returned word of this code has a zero syndrome (or is an abandoned hard decision)
+        sel = torch.from_numpy(mine).to(gpu_device)
+        allpos = ro[sel][:, None] + torch.arange(n, device=gpu_device)[None, :]
+        words = cw[allpos].float()
+        syn = (words @ torch.from_numpy(H.astype(np.float32)).to(gpu_device).T).remainder(2)
+        ok = ab[sel] == 0
+        assert not syn[ok].any(), NAMES[ci]
+        del allpos, words, syn

@@ -146,13 +146,23 @@ def test_ordered_decode_parity(gpu_device, name, ebn0, N):
 
 
 def test_bch_full_size_sampled(gpu_device):
-    """The benchmark's shape (BCH(127,113), 10^6 blocks, budget 10^5, one launch):
-    sampled blocks against the oracle, invariants on every block."""
+    """The benchmark's shape (BCH(127,113), 10^6 blocks, budget 10^5, one launch
+    in the tuned launch shape the benchmark times): sampled blocks against the
+    oracle, invariants on every block, and the same results in the library's
+    default launch shape."""
     print("bch full size", flush=True)
+    from paper_2202_13951_amd import autotune
     H, G = codes.code("bch127_113")
     N, budget = 10 ** 6, 10 ** 5
     llr, _ = channel.awgn_llr(G, N, 4.0, seed=4242)
-    gcw, gq, gab = _gpu_decode(H, llr, budget, gpu_device)
+    knobs = autotune.load_tuned("bch127")
+    assert knobs is not None
+    x = torch.from_numpy(llr).to(gpu_device)
+    cw_t, q_t, ab_t = binding.orbg_decode_ex(H, x, budget, params=binding.LaunchParams(**knobs))
+    torch.cuda.synchronize()
+    gcw, gq, gab = cw_t.cpu().numpy(), q_t.cpu().numpy().astype(np.uint64), ab_t.cpu().numpy()
+    dcw, dq, dab = _gpu_decode(H, llr, budget, gpu_device)
+    assert (dcw == gcw).all() and (dq == gq).all() and (dab == gab).all()
     rng = np.random.default_rng(0)
     idx = np.sort(np.concatenate([rng.choice(N, 400, replace=False), np.argsort(gq)[-50:]]))
     _assert_same((gcw[idx], gq[idx], gab[idx]), O.decode(H, llr[idx], budget, THREADS), "bch sampled")
