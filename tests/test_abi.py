@@ -66,3 +66,36 @@ def test_mixed_rejects_unregistered_and_bad_counts():
     rc = L.orbg_decode_mixed(ids, 9, None, None, None, 0, 100, None, None, None, None, None)
     assert rc == -1 and "ncodes" in L.orbg_last_error().decode()
     assert L.orbg_code_release(777) == -1
+
+
+@pytest.mark.parametrize("n,k,budget,bufs,msg", [
+    (0, 0, 10, True, "n = 0"),
+    (100, 30, 10, True, "n - k = 70"),
+    (32, 26, 0, True, "budget = 0"),
+    (32, 26, (1 << 22) + 1, True, "budget"),
+    (32, 26, 100, False, "device buffer is NULL"),
+])
+def test_1line_argument_errors(n, k, budget, bufs, msg):
+    L = binding.load()
+    m = max(n - k, 1)
+    H = np.zeros((m, max(n, 1)), dtype=np.uint8)
+    p = ctypes.c_void_p(8) if bufs else None
+    rc = L.orbg_decode_1line(H.ctypes.data_as(ctypes.c_void_p), p, n, k, budget, 4, p, p, p, None, None, None)
+    assert rc == -1 and msg in L.orbg_last_error().decode()
+
+
+@pytest.mark.parametrize("n,budget,j0,count,msg", [
+    (0, 100, 0, 10, "n = 0"),
+    (32, 0, 0, 10, "budget"),
+    (8, 300, 0, 10, "budget"),            # more than 2^n patterns
+    (32, 100, 0, 101, "above the budget"),
+    (32, 100, -2, 10, "j0 = -2"),
+    (32, 100, 1 << 20, 10, "j0 = 1048576"),
+])
+def test_1line_export_argument_errors(n, budget, j0, count, msg):
+    L = binding.load()
+    out = np.zeros((max(count, 1), 16), dtype=np.uint8)
+    jm = ctypes.c_int(0)
+    rc = L.orbg_schedule_export_1line(n, budget, j0, count, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(jm),
+                                      None)
+    assert rc == -1 and msg in L.orbg_last_error().decode()
