@@ -87,6 +87,38 @@ def wilson(k: int, n: int, z: float = 1.96):
     return (max(0.0, c - h), min(1.0, c + h))
 
 
+_PAIR = []
+
+
+def warm_events(stream):
+    """One reusable pair of timing events, each recorded once already: torch makes
+    an event's HIP object at its first record, and a fresh pair around a single
+    launch has been measured to add a few hundred microseconds to the interval."""
+    import torch
+    if not _PAIR:
+        pair = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        for e in pair:
+            e.record(stream)
+        torch.cuda.synchronize()
+        _PAIR.extend(pair)
+    return _PAIR[0], _PAIR[1]
+
+
+def time_calls(fn, stream, reps: int = 1) -> float:
+    """Milliseconds per call of fn(): `reps` back-to-back calls between the warm
+    events (with reps > 1 the host's launch time of all calls but the first hides
+    behind the GPU's work)."""
+    import torch
+    a, b = warm_events(stream)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 def algorithmic_ops(q_sum: int, n_sorted: int, n: int) -> float:
     """Integer work the method needs: 4 int32 ops per counted query (one 64-bit
     syndrome XOR and one 64-bit zero test) plus, for each block that needs the
@@ -247,6 +279,9 @@ def run_single(args, wl, dev):
         binding.orbg_decode_ex(H, llr, budget, params=params, out=out)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev:                                 # each event recorded once before the clock
+        a_.record(stream)
+        b_.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -276,12 +311,8 @@ def run_single(args, wl, dev):
     for p, e in enumerate([] if args.no_per_point else wl["ebn0"]):
         sl = slice(p * B, (p + 1) * B)
         sub_out = (cw[sl], q[sl], ab[sl])
-        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a_.record(stream)
-        binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=sub_out)
-        b_.record(stream)
-        torch.cuda.synchronize()
-        t = a_.elapsed_time(b_) / 1e3
+        t = time_calls(lambda: binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=sub_out), stream,
+                       reps=3) / 1e3
         per_point[f"{e:.1f}"]["blocks_per_s"] = B / t
         per_point[f"{e:.1f}"]["queries_per_s"] = float(q_np[sl].sum()) / t
 
@@ -348,6 +379,9 @@ def run_oneline(args, wl, dev):
     for _ in range(args.warmup):
         one()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev:                                 # each event recorded once before the clock
+        a_.record(stream)
+        b_.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -388,19 +422,12 @@ def run_oneline(args, wl, dev):
               "j0": {"mean": float(jp.mean()), "min": int(jp.min()), "max": int(jp.max()),
                      "share": {("9+" if v == 9 else str(int(v))): float(c / B) for v, c in zip(vals, cnts)},
                      "above_j0max": float((jp > j0max).mean())}}
-        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a_.record(stream)
-        binding.orbg_decode_1line(H, llr[sl], budget, j0=False, params=params, out=(cw[sl], q[sl], ab[sl]))
-        b_.record(stream)
-        torch.cuda.synchronize()
-        t = a_.elapsed_time(b_) / 1e3
+        t = time_calls(lambda: binding.orbg_decode_1line(H, llr[sl], budget, j0=False, params=params,
+                                                          out=(cw[sl], q[sl], ab[sl])), stream, reps=3) / 1e3
         pt["blocks_per_s"] = B / t
         pt["queries_per_s"] = float(q_np[sl].sum()) / t
-        a_.record(stream)
-        binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=(bcw, bq, bab))
-        b_.record(stream)
-        torch.cuda.synchronize()
-        tb = a_.elapsed_time(b_) / 1e3
+        tb = time_calls(lambda: binding.orbg_decode_ex(H, llr[sl], budget, params=params, out=(bcw, bq, bab)),
+                        stream, reps=3) / 1e3
         berr = (bcw != sent[sl]).any(dim=1).cpu().numpy()
         bq_np = bq.cpu().numpy()
         nb = int(berr.sum())
@@ -461,12 +488,7 @@ def run_mixed(args, wl, dev):
     points, tot_blocks, tot_ms, tot_naive_ms, tot_q = {}, 0, 0.0, 0.0, 0
 
     def timed(fn):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b)
+        return time_calls(fn, stream)
 
     for e in wl["ebn0"]:
         HG, llr, sent, bc, ro = mixed_inputs(wl, e, dev)
@@ -533,9 +555,11 @@ def run_mixed(args, wl, dev):
 
 def run_stream(args, wl, dev):
     """Serving loop over a Poisson request stream.  Arrivals are on the host clock
-    (perf_counter from t0); completions on the GPU clock, as the elapsed time from an
-    event recorded at t0 to the event recorded after each launch.  Latency =
-    completion - arrival.  Every result is compared with one decode of all requests."""
+    (perf_counter from t0); completions on the GPU clock, as the elapsed time from a
+    reference event e0 to the event recorded after each launch, moved to the host
+    clock by an offset bracketed with record-and-wait round trips before t0.
+    Latency = completion - arrival.  Every result is compared with one decode of
+    all requests."""
     import collections
     import torch
     from paper_2202_13951_amd import binding
@@ -566,19 +590,39 @@ def run_stream(args, wl, dev):
         torch.cuda.synchronize()
         inflight, batches = [collections.deque() for _ in streams], []
         n_in, nxt, k = 0, 0, 0
+        # completion events come from a pool recorded once before the clock (a
+        # fresh event would be made on the clock); an event goes back to the pool
+        # once its completion time has been read
+        pool = [torch.cuda.Event(enable_timing=True) for _ in range(4096)]
+        for ev in pool:
+            ev.record(s)
+        torch.cuda.synchronize()
+        fresh = 0
         gc.collect()
         gc.disable()                                  # no collector pauses on the clock
-        e0 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
+        # GPU clock (event times since e0) against the host clock: each round trip
+        # "host time, record, wait, host time" brackets one GPU stamp, so the
+        # offset host(e0) - t0 lies in [off_lo, off_hi], the narrowest bracket
+        # setting the width
+        e0, ec = pool.pop(), pool.pop()               # both recorded once already
         e0.record(s)
         torch.cuda.synchronize()
-        align = time.perf_counter() - t0              # bound on the host/GPU clock offset
+        cal = []
+        for _ in range(32):
+            ta = time.perf_counter()
+            ec.record(s)
+            ec.synchronize()
+            cal.append((ta, time.perf_counter(), e0.elapsed_time(ec) / 1e3))
+        t0 = time.perf_counter()
+        off_lo = max(ta - t0 - tg for ta, _, tg in cal)
+        off_hi = min(tb - t0 - tg for _, tb, tg in cal)
         while nxt < N or any(inflight):
             for fl in inflight:
                 while fl and fl[0][0].query():
                     ev, lo, hi = fl.popleft()
                     n_in -= hi - lo
-                    batches.append((ev, lo, hi, time.perf_counter() - t0))
+                    batches.append((e0.elapsed_time(ev) / 1e3, lo, hi, time.perf_counter() - t0))
+                    pool.append(ev)
             if nxt < N:
                 j = int(np.searchsorted(t_arr, time.perf_counter() - t0, side="right"))
                 j = min(j, nxt + wl["max_batch"], nxt + wl["capacity"] - n_in)
@@ -586,7 +630,11 @@ def run_stream(args, wl, dev):
                     st = streams[k]
                     binding.orbg_decode_mixed(ids, bc[nxt:j], ro[nxt:j], llr, wl["budget"], cw, q[nxt:j],
                                               ab[nxt:j], params=params, stream=st)
-                    ev = torch.cuda.Event(enable_timing=True)
+                    if pool:
+                        ev = pool.pop()
+                    else:
+                        ev = torch.cuda.Event(enable_timing=True)
+                        fresh += 1
                     ev.record(st)
                     inflight[k].append((ev, nxt, j))
                     k = (k + 1) % len(streams)
@@ -594,11 +642,13 @@ def run_stream(args, wl, dev):
                     nxt = j
         torch.cuda.synchronize()
         gc.enable()
-        # completion on the GPU clock (a lower bound: the GPU stamps e0 a little
-        # after t0) and as first seen by the host loop (an upper bound)
+        # completion on the GPU clock moved to the host clock (between the two ends
+        # of the offset bracket; the lower end is reported, the upper end differs
+        # by the bracket's width) and as first seen by the host loop (an upper
+        # bound: the loop polls)
         done, seen = np.empty(N), np.empty(N)
-        for ev, lo, hi, th in batches:
-            done[lo:hi] = e0.elapsed_time(ev) / 1e3
+        for tg, lo, hi, th in batches:
+            done[lo:hi] = tg + off_lo
             seen[lo:hi] = th
         lat = (done - t_arr) * 1e6
         lat_host = (seen - t_arr) * 1e6
@@ -627,8 +677,8 @@ def run_stream(args, wl, dev):
                            "mean": float(lat.mean())},
             "latency_host_us": {"p50": float(np.percentile(lat_host, 50)),
                                 "p99": float(np.percentile(lat_host, 99)), "max": float(lat_host.max())},
-            "launches": len(batches), "mean_launch_blocks": float(sizes.mean()),
-            "max_launch_blocks": int(sizes.max()), "clock_alignment_us": align * 1e6,
+            "launches": len(batches), "events_made_on_clock": fresh, "mean_launch_blocks": float(sizes.mean()),
+            "max_launch_blocks": int(sizes.max()), "clock_offset_bracket_us": (off_hi - off_lo) * 1e6,
             "queries_per_s": float(q.sum()) / span, "identical_to_one_decode": same, "per_code": per_code}
         print(f"stream {rate:.0e}/s: p50 {np.percentile(lat, 50):.0f} us p99 {np.percentile(lat, 99):.0f} us, "
               f"{N / span:.3g} blocks/s, {len(batches)} launches", file=sys.stderr, flush=True)
@@ -677,12 +727,9 @@ def run_learned(args, wl, dev):
     del x, y
 
     def timed(fn):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        r = fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return r, a.elapsed_time(b) / 1e3
+        out = []
+        ms = time_calls(lambda: out.append(fn()), stream)
+        return out[0], ms / 1e3
 
     points = {}
     tot = dict(blocks=0, plain_s=0.0, learned_s=0.0, plain_q=0, learned_q=0)
