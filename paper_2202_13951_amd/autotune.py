@@ -32,14 +32,25 @@ KNOBS = {
 DEFAULT = dict(workgroups_per_cu=32, chunk=0, split_steps=64, heavy_waves=8, heavy_workgroups_per_cu=2)
 
 
+_EVENTS = []
+
+
 def time_launch(run, params, reps: int = 3) -> float:
-    """Median milliseconds of `run(params)` (one decode on torch's current stream)."""
+    """Median milliseconds of `run(params)` (one decode on torch's current stream).
+    One pair of events serves every measurement, recorded once before the first:
+    torch makes an event's HIP object at its first record, which would stretch
+    the first interval it bounds."""
     import torch
     stream = torch.cuda.current_stream()
+    if not _EVENTS:
+        _EVENTS.extend(torch.cuda.Event(enable_timing=True) for _ in range(2))
+        for e in _EVENTS:
+            e.record(stream)
+    a, b = _EVENTS
     run(params)                                       # warm-up (caches, work space)
+    torch.cuda.synchronize()
     times = []
     for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         run(params)
         b.record(stream)
