@@ -48,7 +48,7 @@ WORKLOADS = {
                    desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
                         "budget 1e5, plain ORBGRAND"),
     "bch127_1line": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
-                         blocks=10 ** 6, budget=10 ** 5, oneline=True, tuned_as="bch127",
+                         blocks=10 ** 6, budget=10 ** 5, oneline=True,
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
                               "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. IV) against basic ORBGRAND "
                               "on the same blocks"),
@@ -253,6 +253,9 @@ def make_runner(name: str):
     H, llr, sent = single_inputs(wl, dev)
     out = (torch.empty_like(sent), torch.empty(llr.shape[0], dtype=torch.int64, device=dev),
            torch.empty(llr.shape[0], dtype=torch.uint8, device=dev))
+    if wl.get("oneline"):
+        return (lambda p: binding.orbg_decode_1line(H, llr, wl["budget"], j0=False, params=p, out=out)), \
+            llr.shape[0]
     return (lambda p: binding.orbg_decode_ex(H, llr, wl["budget"], params=p, out=out)), llr.shape[0]
 
 
@@ -366,7 +369,7 @@ def run_oneline(args, wl, dev):
     H, llr, sent = single_inputs(wl, dev)
     n, budget = wl["n"], wl["budget"]
     P, B = len(wl["ebn0"]), wl["blocks"]
-    params, knobs = tuned_params(wl.get("tuned_as", args.workload), not args.no_tuned)
+    params, knobs = tuned_params(args.workload, not args.no_tuned)
     cw = torch.empty_like(sent)
     q = torch.empty((P * B,), dtype=torch.int64, device=dev)
     ab = torch.empty((P * B,), dtype=torch.uint8, device=dev)

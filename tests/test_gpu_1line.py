@@ -175,7 +175,7 @@ def test_bch_full_size_sampled(gpu_device):
     H, G = codes.code("bch127_113")
     N, budget = 10 ** 6, 10 ** 5
     llr, _ = channel.awgn_llr(G, N, 5.0, seed=5151)
-    tuned = binding.LaunchParams(**autotune.load_tuned("bch127"))      # the shape the benchmark times
+    tuned = binding.LaunchParams(**autotune.load_tuned("bch127_1line"))      # the shape the benchmark times
     gcw, gq, gab, gj = _gpu(H, llr, budget, gpu_device, params=tuned)
     rng = np.random.default_rng(1)
     idx = np.sort(np.concatenate([rng.choice(N, 400, replace=False), np.argsort(gq)[-50:]]))
