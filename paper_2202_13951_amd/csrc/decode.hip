@@ -723,10 +723,14 @@ struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; 
 //      row loaded while the current one is decoded; the two fetch buffers
 //      alternate, so no register copy waits for a load.
 // Waves per SIMD the light pass asks the register allocator for: the device
-// holds 8 (32 per CU); up to 4 keys per lane with 32-bit syndromes fit 64
-// vector registers, wider variants keep the compiler's choice.
+// holds 8 (32 per CU); up to 2 keys per lane with 32-bit syndromes fit 64
+// vector registers; 4 keys per lane run 6 waves (at 8 they spill to scratch,
+// measured slower); wider variants keep the compiler's choice.
 template <int NKMAX, typename S>
-constexpr int light_waves() { return (NKMAX <= 4 && sizeof(S) == 4) ? 8 : 1; }
+constexpr int light_waves()
+{
+    return sizeof(S) != 4 ? 1 : NKMAX <= 2 ? 8 : NKMAX == 4 ? 6 : 1;
+}
 
 template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE>
 __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(light_waves<NKMAX, S>())))
