@@ -722,18 +722,20 @@ struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; 
 //   2. the other blocks (a 64-bit mask) are decoded one by one, the next one's
 //      row loaded while the current one is decoded; the two fetch buffers
 //      alternate, so no register copy waits for a load.
-// Waves per SIMD the light pass asks the register allocator for: the device
-// holds 8 (32 per CU); up to 2 keys per lane with 32-bit syndromes fit 64
-// vector registers; 4 keys per lane run 6 waves (at 8 they spill to scratch,
-// measured slower); wider variants keep the compiler's choice.
-template <int NKMAX, typename S>
+// Waves per SIMD the light pass asks the register allocator for (the device
+// holds at most 8, 32 per CU), chosen by measurement with 32-bit syndromes:
+// 1 key per lane fits 64 vector registers at 8 waves; 2 keys per lane run
+// best at 7 (at 8 some registers go to scratch, at 6 too few waves hide the
+// latency), except in 1-line mode (no first-batch ranking), which runs best
+// at 8; 4 keys per lane at 6; wider variants keep the compiler's choice.
+template <int NKMAX, typename S, bool ONELINE>
 constexpr int light_waves()
 {
-    return sizeof(S) != 4 ? 1 : NKMAX <= 2 ? 8 : NKMAX == 4 ? 6 : 1;
+    return sizeof(S) != 4 ? 1 : NKMAX == 1 ? 8 : NKMAX == 2 ? (ONELINE ? 8 : 7) : NKMAX == 4 ? 6 : 1;
 }
 
 template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE>
-__global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(light_waves<NKMAX, S>())))
+__global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(light_waves<NKMAX, S, ONELINE>())))
 light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
              const float* __restrict__ llr, int64_t nblocks, uint32_t budget, uint32_t split_steps,
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
