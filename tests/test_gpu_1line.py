@@ -188,3 +188,39 @@ def test_bch_full_size_sampled(gpu_device):
     assert not syn[ok].any()
     ncw, nq, nab, _ = _gpu(H, llr, budget, gpu_device, j0=None, params=tuned)
     assert (ncw == gcw).all() and (nq == gq).all() and (nab == gab).all()
+
+
+def test_hip_graph_replay(gpu_device):
+    """The 1-line decode (counter reset, light pass with the offset fit, heavy
+    pass) captured in a graph: every replay, with eager work in between, equals
+    the eager result, offsets included."""
+    print("1-line graph replay", flush=True)
+    H, G = codes.code("bch127_113")
+    llr, _ = channel.awgn_llr(G, 4000, 4.5, seed=808)
+    x = torch.from_numpy(llr).to(gpu_device)
+    budget = 10 ** 5
+    params = binding.LaunchParams(split_steps=8)                # the heavy pass takes part
+    eager = _gpu(H, llr, budget, gpu_device, params=params)
+    N, n = llr.shape
+    s = torch.cuda.Stream()
+    cw = torch.zeros((N, n), dtype=torch.uint8, device=gpu_device)
+    q = torch.zeros(N, dtype=torch.int64, device=gpu_device)
+    ab = torch.zeros(N, dtype=torch.uint8, device=gpu_device)
+    j0 = torch.zeros(N, dtype=torch.int32, device=gpu_device)
+    with torch.cuda.stream(s):                                  # warm-up: schedules, work space
+        binding.orbg_decode_1line(H, x, budget, j0=j0, params=params, out=(cw, q, ab), stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        binding.orbg_decode_1line(H, x, budget, j0=j0, params=params, out=(cw, q, ab), stream=s)
+    for rep in range(3):
+        cw.fill_(7)
+        q.fill_(-1)
+        ab.fill_(9)
+        j0.fill_(-9)
+        _gpu(H, llr, budget, gpu_device, params=params)         # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = (cw.cpu().numpy(), q.cpu().numpy().astype(np.uint64), ab.cpu().numpy(), j0.cpu().numpy())
+        _assert_same(got, eager, f"replay {rep}")
+    assert (eager[1] > 8 * 64).any()                            # some blocks reached the heavy pass
