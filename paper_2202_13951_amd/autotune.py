@@ -125,6 +125,15 @@ def main():
     run, blocks = bench.make_runner(args.workload)
     default_ms = time_launch(run, LaunchParams(**DEFAULT))
     best, ms, hist = tune(run, rounds=args.rounds, log=lambda s: print(s, flush=True))
+    # single timings differ by a few percent, so the descent can end on a worse
+    # shape than one found before: the cached shape, if any, meets the new one
+    # in a final comparison with more repetitions, and the faster is kept
+    prev = load_tuned(args.workload, args.out) or load_tuned(args.workload)
+    if prev and prev != best:
+        new_ms = time_launch(run, LaunchParams(**best), 9)
+        prev_ms = time_launch(run, LaunchParams(**prev), 9)
+        print(f"new {best} {new_ms:.3f} ms, cached {prev} {prev_ms:.3f} ms", flush=True)
+        best, ms = (prev, prev_ms) if prev_ms < new_ms else (best, new_ms)
     print(json.dumps({"workload": args.workload, "blocks": blocks, "default_ms": default_ms, "best_ms": ms,
                       "params": best, "evaluations": len(hist)}), flush=True)
     save_tuned(args.workload, best, ms, default_ms, args.out)
