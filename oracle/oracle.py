@@ -31,8 +31,10 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP); returns the library path."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, "-lm"])
+        # no contraction into fused multiply-adds: the FP32 fits run in the
+        # order the source writes
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-shared",
+                               "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +67,15 @@ def lib():
         L.oracle_decode_1line.restype = ctypes.c_int
         L.oracle_decode_1line.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_long,
                                           u8p, u8p, u8p, u8p, ctypes.c_long, ctypes.c_int]
+        lp = ctypes.POINTER(ctypes.c_long)
+        L.oracle_order_mline_prefix.restype = ctypes.c_long
+        L.oracle_order_mline_prefix.argtypes = [ctypes.c_int, ctypes.c_int, i32p, lp, lp, ctypes.c_long,
+                                                ctypes.c_int, i32p, i32p]
+        L.oracle_fit_mline.restype = ctypes.c_int
+        L.oracle_fit_mline.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, i32p, lp, lp]
+        L.oracle_decode_mline.restype = ctypes.c_int
+        L.oracle_decode_mline.argtypes = [u8p, u8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_long,
+                                          ctypes.c_int, ctypes.c_int, u8p, u8p, u8p, u8p, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -213,3 +224,67 @@ def decode_1line(H: np.ndarray, llr: np.ndarray, budget: int, threads: int = 1, 
                                    NO_FORCE if j0_force is None else int(j0_force), threads)
     assert rc == 0, rc
     return cw, q, ab, j0
+
+
+# ---------------------------------------------------------------------------
+# Full (m-line) ORBGRAND (Sec. IV; readings R12-R15 in the C source)
+# ---------------------------------------------------------------------------
+MMAX = 8
+
+
+def order_mline_prefix(n: int, I, J, beta, count: int, width: int = 32) -> list[tuple[int, ...]]:
+    """First `count` patterns of the m-line order of the model (I[0..m], J[0..m-1],
+    beta[0..m-1]) as 1-based rank tuples."""
+    m = len(J)
+    Ia = np.ascontiguousarray(I, dtype=np.int32)
+    Ja = np.ascontiguousarray(J, dtype=np.int64)
+    Ba = np.ascontiguousarray(beta, dtype=np.int64)
+    assert Ia.shape[0] == m + 1 and Ba.shape[0] == m
+    out = np.zeros((count, width), dtype=np.int32)
+    wout = np.zeros(count, dtype=np.int32)
+    lp = ctypes.POINTER(ctypes.c_long)
+    i32p = ctypes.POINTER(ctypes.c_int)
+    got = lib().oracle_order_mline_prefix(n, m, Ia.ctypes.data_as(i32p), Ja.ctypes.data_as(lp),
+                                          Ba.ctypes.data_as(lp), count, width, out.ctypes.data_as(i32p),
+                                          wout.ctypes.data_as(i32p))
+    if got == -2:
+        raise ValueError("invalid model")
+    if got < 0:
+        raise ValueError("pattern wider than the row width")
+    return [tuple(int(x) for x in out[g, :wout[g]]) for g in range(got)]
+
+
+def fit_mline(llr: np.ndarray, mreq: int, jdiv: bool = False):
+    """Model of one block (1-D float32 LLRs) with at most mreq segments:
+    returns (I, J, beta) as lists, len(J) = len(beta) = m, len(I) = m + 1."""
+    x = np.ascontiguousarray(llr, dtype=np.float32)
+    m = ctypes.c_int(0)
+    I = np.zeros(MMAX + 1, dtype=np.int32)
+    J = np.zeros(MMAX, dtype=np.int64)
+    B = np.zeros(MMAX, dtype=np.int64)
+    lp = ctypes.POINTER(ctypes.c_long)
+    i32p = ctypes.POINTER(ctypes.c_int)
+    rc = lib().oracle_fit_mline(_ptr(x), x.shape[0], int(mreq), int(bool(jdiv)), ctypes.byref(m),
+                                I.ctypes.data_as(i32p), J.ctypes.data_as(lp), B.ctypes.data_as(lp))
+    if rc != 0:
+        raise ValueError("oracle_fit_mline rejected its arguments")
+    mm = m.value
+    return [int(v) for v in I[:mm + 1]], [int(v) for v in J[:mm]], [int(v) for v in B[:mm]]
+
+
+def decode_mline(H: np.ndarray, llr: np.ndarray, budget: int, mreq: int, jdiv: bool = False, threads: int = 1):
+    """m-line ORBGRAND decode; returns (codewords u8 [N, n], queries u64 [N], abandoned u8 [N],
+    segment counts i32 [N])."""
+    H = np.ascontiguousarray(H, dtype=np.uint8)
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float32)
+    N, n = llr.shape
+    k = n - H.shape[0]
+    cw = np.zeros((N, n), dtype=np.uint8)
+    q = np.zeros(N, dtype=np.uint64)
+    ab = np.zeros(N, dtype=np.uint8)
+    ms = np.zeros(N, dtype=np.int32)
+    rc = lib().oracle_decode_mline(_ptr(H), _ptr(llr), n, k, int(budget), N, int(mreq), int(bool(jdiv)),
+                                   _ptr(cw), _ptr(q), _ptr(ab), _ptr(ms), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_decode_mline rejected its arguments")
+    return cw, q, ab, ms
