@@ -147,6 +147,32 @@ int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t
                       int32_t* j0, const orbg_launch_params* params, void* stream);
 
 /*
+ * Full (m-line) ORBGRAND decode (Sec. IV): per block, a piecewise-linear fit of
+ * the sorted reliabilities with at most `segments` lines (anchor points from
+ * ranks 1 and floor(n/2), each added anchor at the rank with the largest
+ * vertical gap to the chord of its neighbouring anchors, smallest rank on
+ * ties; no anchor is added when the largest gap is 0), quantized by eqs. (Q)
+ * and (quant) in FP32 (round half up, capped at 2^20; a slope that is not
+ * positive and finite gives the basic model); with jdiv = 1 each J_{i-1} is
+ * then rounded to a multiple of beta_i (the J/beta variant).  Queries follow
+ * eq. (cartP): reliability weight ascending, then the splitting patterns in the
+ * nested-loop order of the integer splitting algorithm, then the Cartesian
+ * product of the per-segment partial sets (segment 1 outermost; each partial
+ * set by Hamming weight, then Landslide order).  Same H, llr, codeword,
+ * queries, abandoned layouts and rules as orbg_decode.
+ * Limits: 1 <= n <= 128, 1 <= n - k <= 64, 1 <= segments <= 4, jdiv 0 or 1,
+ * 1 <= budget <= 2^16 (within that budget no query has more than 16 flips in a
+ * segment, which bounds the device tables).  segments_out: DEVICE i32 per
+ * block, the number of lines the fit used, or NULL.  The first call on a device
+ * builds an 18 MB table of subset counts (allocates and synchronises
+ * `stream`).  Errors: ORBG_EINVAL for arguments outside these limits, as
+ * orbg_decode otherwise.
+ */
+int orbg_decode_mline(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
+                      int64_t batch, int segments, int jdiv, uint8_t* codeword, uint64_t* queries,
+                      uint8_t* abandoned, int32_t* segments_out, void* stream);
+
+/*
  * Registers a parity-check matrix (host, as for orbg_decode) for mixed-code
  * decodes and returns its id in *code_id.  Registering the same H twice gives
  * two ids for one cached copy.  Allocates and synchronises the device on first

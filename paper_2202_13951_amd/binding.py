@@ -79,6 +79,8 @@ def load():
     L.orbg_decode_1line.restype = ci
     L.orbg_schedule_export_1line.argtypes = [ci, u64, ci, u64, vp, ctypes.POINTER(ci), vp]
     L.orbg_schedule_export_1line.restype = ci
+    L.orbg_decode_mline.argtypes = [vp, vp, ci, ci, u64, i64, ci, ci, vp, vp, vp, vp, vp]
+    L.orbg_decode_mline.restype = ci
     L.orbg_last_error.argtypes = []
     L.orbg_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -192,6 +194,32 @@ def orbg_decode_1line(H, llr, budget: int, j0=True, params: LaunchParams | None 
                                   _stream_ptr(stream))
     _check("orbg_decode_1line", rc)
     return cw, q, ab, j0
+
+
+def orbg_decode_mline(H, llr, budget: int, segments: int, jdiv: bool = False, segments_out=True, out=None,
+                      stream=None):
+    """Full m-line ORBGRAND decode.  segments_out: True (allocate), a CUDA int32 [N] tensor,
+    or None/False.  Returns (codeword, queries, abandoned, segments_out or None)."""
+    import torch
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    assert llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()
+    assert llr.dim() == 2 and llr.shape[1] == n
+    N = llr.shape[0]
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    if segments_out is True:
+        segments_out = torch.empty((N,), dtype=torch.int32, device=llr.device)
+    elif segments_out is False:
+        segments_out = None
+    if segments_out is not None:
+        assert (segments_out.is_cuda and segments_out.dtype == torch.int32 and segments_out.is_contiguous()
+                and segments_out.shape[0] == N)
+    rc = load().orbg_decode_mline(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
+                                  int(budget), N, int(segments), int(bool(jdiv)), ctypes.c_void_p(cw.data_ptr()),
+                                  ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(ab.data_ptr()), _p(segments_out),
+                                  _stream_ptr(stream))
+    _check("orbg_decode_mline", rc)
+    return cw, q, ab, segments_out
 
 
 def orbg_code_register(H) -> int:

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +18,7 @@
 #include "orbg_internal.h"
 #include "orbg_kernels.h"
 #include "orbg_mlp.h"
+#include "orbg_mline.h"
 
 namespace {
 
@@ -314,6 +316,30 @@ int check_budget(uint64_t budget, int64_t batch)
     return ORBG_OK;
 }
 
+// device -> subset-count table of the m-line order (built once per device)
+std::map<int, uint32_t*> g_ml_table;
+
+int get_ml_table(hipStream_t st, const uint32_t** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ml_table.find(dev);
+    if (it != g_ml_table.end()) { *out = it->second; return ORBG_OK; }
+    uint32_t* t = nullptr;
+    if (hipMalloc(&t, sizeof(uint32_t) * orbg::subset_table_words()) != hipSuccess)
+        return fail(ORBG_ENOMEM, "cannot allocate the subset-count table");
+    hipError_t e = orbg::build_subset_table(t, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(t);
+        return fail(ORBG_EHIP, "subset-count table build failed: %s", hipGetErrorString(e));
+    }
+    g_ml_table.emplace(dev, t);
+    *out = t;
+    return ORBG_OK;
+}
+
 int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
                   const orbg_launch_params* params, void* stream, bool oneline = false, int32_t* j0 = nullptr)
@@ -390,6 +416,52 @@ int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t
     g_err.clear();
     return decode_single(H, llr, n, k, budget, batch, nullptr, codeword, queries, abandoned, params, stream, true,
                          j0);
+}
+
+int orbg_decode_mline(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                      int segments, int jdiv, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
+                      int32_t* segments_out, void* stream)
+{
+    g_err.clear();
+    int rc = check_code_args(H, n, k);
+    if (rc) return rc;
+    if (n > ORBG_ML_LMAX) return fail(ORBG_EINVAL, "n = %d above %d for the m-line order", n, ORBG_ML_LMAX);
+    if (segments < 1 || segments > ORBG_ML_MSEG)
+        return fail(ORBG_EINVAL, "segments = %d outside [1, %d]", segments, ORBG_ML_MSEG);
+    if (jdiv != 0 && jdiv != 1) return fail(ORBG_EINVAL, "jdiv = %d is not 0 or 1", jdiv);
+    if (budget < 1 || budget > ORBG_ML_BUDGET_MAX)
+        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^16] for the m-line order", (unsigned long long)budget);
+    if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
+    if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
+        return fail(ORBG_EINVAL, "a device buffer is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CodeEntry* code = nullptr;
+    if ((rc = get_code(H, n, k, &code))) return rc;
+    const uint32_t* tbl = nullptr;
+    if ((rc = get_ml_table(st, &tbl))) return rc;
+    if (batch == 0) return ORBG_OK;
+    Workspace* w = nullptr;
+    int cus = 0;
+    if ((rc = get_workspace(st, 0, &w, &cus))) return rc;
+    orbg::MlineArgs a;
+    a.llr = llr;
+    a.n = n;
+    a.m = n - k;
+    a.cols = code->d_cols;
+    a.rows = code->d_rows;
+    a.nblocks = batch;
+    a.budget = (uint32_t)budget;
+    a.mseg = segments;
+    a.jdiv = jdiv != 0;
+    a.table = tbl;
+    a.cw = codeword;
+    a.queries = queries;
+    a.abandoned = abandoned;
+    a.mfit = segments_out;
+    const int64_t grid = std::min<int64_t>(batch, (int64_t)cus * 32);
+    const hipError_t e = orbg::launch_mline(a, (int)grid, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "m-line decode launch failed: %s", hipGetErrorString(e));
+    return ORBG_OK;
 }
 
 int orbg_code_register(const uint8_t* H, int n, int k, int* code_id)

@@ -1,0 +1,575 @@
+// Full (m-line) ORBGRAND decode kernel for gfx950 (Sec. IV).
+//
+// Per block, one wave:
+//   1. the LLR row (n <= 128: one or two elements per lane), hard decision and
+//      base syndrome s0 (Sec. III-A); s0 == 0 is query 1;
+//   2. the full reliability order: keys (IEEE bits of |LLR|) << 32 | index sorted
+//      ascending by a register bitonic network; h_r = column of rank r, pi_r its
+//      received index and L_r its magnitude go to LDS;
+//   3. the piecewise-linear fit (anchor points from ranks 1 and floor(n/2),
+//      each added anchor at the largest vertical gap to the chord of its two
+//      neighbours, the gaps of all candidate ranks computed one per lane) and
+//      the quantization of eqs. (Q) and (quant), every FP32 operation rounded to
+//      nearest in the written order; optionally J_{i-1} rounded to a multiple of
+//      beta_i (the J/beta variant);
+//   4. the query order of eq. (cartP): reliability weights W ascending; inside
+//      one W the splitting patterns (W_1, ..., W_m) in the nested-loop order of
+//      the integer splitting algorithm, each W_i among the partial weights its
+//      segment can take (the collection step); inside one split the Cartesian
+//      product of the partial sets, segment 1 outermost, each partial set by
+//      partial Hamming weight, then Landslide (= lexicographic) order.  The
+//      patterns of one split are tested 64 at a time: lane l takes product
+//      element base + l and unranks it (mixed radix over the segments, then the
+//      Hamming weight, then a lexicographic subset of the segment's ranks with
+//      the given sum) with a table of subset counts; a ballot of syndrome == 0
+//      gives the first member in order;
+//   5. codeword, queries, abandon flag; optionally the block's segment count.
+//
+// Exactness limits (checked by the host): n <= 128, n - k <= 64, m <= 4,
+// budget <= 2^16.  A pattern with 17 or more flips inside one segment comes
+// after all 2^17 - 1 patterns made of proper subsets of its flips (each weighs
+// less, or the same with fewer flips, since every rank but rank 1 weighs at
+// least 1), so no query within 2^16 has more than 16 flips in a segment and
+// partial logistic weights stay below 16 * 128; the count table covers exactly
+// that range, and the order restricted to it agrees with the full order on its
+// first 2^17 patterns.
+#include "orbg_device.h"
+#include "orbg_internal.h"
+#include "orbg_mline.h"
+
+namespace orbg {
+
+namespace {
+
+constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..16
+constexpr int SL = ORBG_ML_SMAX;          // partial logistic weights 0..2047
+constexpr int64_t NONE = INT64_MAX;
+
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Subset counts: number of w-subsets of {1..len} with sum s, saturated.
+__device__ __forceinline__ uint32_t subset_count(const uint32_t* __restrict__ tbl, int64_t len, int64_t w, int64_t s)
+{
+    if (len < 0 || len > ORBG_ML_LMAX || w < 0 || w > WL || s < 0 || s >= SL) return 0u;
+    return tbl[((size_t)len * (WL + 1) + (size_t)w) * SL + (size_t)s];
+}
+
+__device__ __forceinline__ int64_t lw_min(int64_t w) { return w * (w + 1) / 2; }
+__device__ __forceinline__ int64_t lw_max(int64_t w, int64_t len) { return w * len - w * (w - 1) / 2; }
+
+// One segment of the model: offset J_{i-1}, slope beta_i, first rank - 1, length.
+struct Seg {
+    int64_t J, B;
+    int off, len;
+};
+
+__device__ __forceinline__ int wcap(const Seg& g) { return g.len < WL ? g.len : WL; }
+
+// Relative logistic weight of w >= 1 flips with partial weight x, or -1.
+__device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
+{
+    const int64_t r = x - (int64_t)w * g.J;
+    if (r < 0 || r % g.B != 0) return -1;
+    const int64_t wp = r / g.B;
+    return (wp < lw_min(w) || wp > lw_max(w, g.len)) ? -1 : wp;
+}
+
+// Number of partial patterns (at most 16 flips) of the segment with partial
+// weight x; the empty one has weight 0.
+__device__ uint64_t seg_count(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x)
+{
+    uint64_t c = x == 0 ? 1u : 0u;
+    const int wc = wcap(g);
+    for (int w = 1; w <= wc; ++w) {
+        const int64_t wp = rel_weight(g, x, w);
+        if (wp >= 0) c += subset_count(tbl, g.len, w, wp);
+    }
+    return c;
+}
+
+// Smallest partial weight >= x the segment can take (NONE if none).
+__device__ int64_t seg_next(const Seg& g, int64_t x)
+{
+    if (x <= 0) return 0;
+    int64_t best = NONE;
+    const int wc = wcap(g);
+    for (int w = 1; w <= wc; ++w) {
+        const int64_t lo = lw_min(w), hi = lw_max(w, g.len), need = x - (int64_t)w * g.J;
+        int64_t wp = need <= 0 ? lo : (need + g.B - 1) / g.B;
+        if (wp < lo) wp = lo;
+        if (wp > hi) continue;
+        const int64_t c = (int64_t)w * g.J + g.B * wp;
+        if (c < best) best = c;
+    }
+    return best;
+}
+
+template <int M>
+struct Walk {
+    Seg seg[M];
+    int64_t a[M];           // current split
+    uint64_t cnt[M];        // partial-set sizes of the split
+    uint64_t qbase;         // patterns tested before the current split
+    uint32_t budget;
+    uint64_t s0;
+    const uint32_t* tbl;
+    const uint64_t* h;      // LDS: column of each rank
+    uint8_t* win;           // LDS: the winner's ranks
+    int nwin;
+    bool stop, found;
+    uint32_t q;
+};
+
+// Lexicographic unranking of a w-subset of {1..len} with sum s: index u (0-based)
+// among those subsets in ascending order of (v_1, v_2, ...).  emit(v) per element.
+template <typename F>
+__device__ __forceinline__ void unrank_subset(const uint32_t* __restrict__ tbl, int len, int w, int64_t s, uint64_t u,
+                                              F&& emit)
+{
+    int prev = 0;
+    for (int k = 1; k <= w; ++k) {
+        const int rw = w - k;
+        int c = prev + 1;
+        for (; c <= len; ++c) {
+            // the rw elements after v_k = c come from {c+1..len} with sum s - c,
+            // i.e. (shifted by c) from {1..len-c} with sum s - c - rw c
+            const uint64_t n = subset_count(tbl, len - c, rw, s - c - (int64_t)rw * c);
+            if (u < n) break;
+            u -= n;
+        }
+        if (c > len) c = len;                 // exact counts always stop the scan before
+        emit(c);
+        s -= c;
+        prev = c;
+    }
+}
+
+// Element u of the partial set of segment g for partial weight x: Hamming
+// weight ascending (the empty pattern first), lexicographic inside.
+template <typename F>
+__device__ __forceinline__ void unrank_partial(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x, uint64_t u,
+                                               F&& emit)
+{
+    if (x == 0) {
+        if (u == 0) return;                   // the empty partial pattern
+        u -= 1;
+    }
+    const int wc = wcap(g);
+    for (int w = 1; w <= wc; ++w) {
+        const int64_t wp = rel_weight(g, x, w);
+        if (wp < 0) continue;
+        const uint64_t n = subset_count(tbl, g.len, w, wp);
+        if (u < n) {
+            unrank_subset(tbl, g.len, w, wp, u, [&](int v) { emit(g.off + v); });
+            return;
+        }
+        u -= n;
+    }
+}
+
+// Product element u of the current split, segment 1 outermost.
+template <int M, typename F>
+__device__ __forceinline__ void unrank_product(const Walk<M>& c, uint64_t u, F&& emit)
+{
+    uint64_t t[M];
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        t[i] = (i == 0) ? u : u % c.cnt[i];
+        u = (i == 0) ? 0 : u / c.cnt[i];
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) unrank_partial(c.tbl, c.seg[i], c.a[i], t[i], emit);
+}
+
+__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b)
+{
+    const uint64_t cap = 1ull << 40;
+    if (a == 0 || b == 0) return 0;
+    if (a >= cap || b >= cap || a > cap / b) return cap;
+    return a * b;
+}
+
+// Tests the current split's patterns in order, 64 per step.
+template <int M>
+__device__ void run_split(Walk<M>& c)
+{
+    const int lane = lane_id();
+    uint64_t count = 1;
+#pragma unroll
+    for (int i = 0; i < M; ++i) count = sat_mul(count, c.cnt[i]);
+    const uint64_t left = (uint64_t)c.budget - c.qbase;        // > 0 while the walk runs
+    const uint64_t lim = count < left ? count : left;
+    for (uint64_t base = 0; base < lim; base += ORBG_WAVE) {
+        const uint64_t u = base + (uint64_t)lane;
+        const bool act = u < lim;
+        uint64_t s = c.s0;
+        if (act) unrank_product(c, u, [&](int r) { s ^= c.h[r]; });
+        const uint64_t hits = ballot(act && s == 0);
+        if (hits != 0) {
+            const int wl = __builtin_ctzll(hits);
+            c.q = (uint32_t)(c.qbase + base + (uint64_t)wl + 1);
+            c.found = true;
+            c.stop = true;
+            if (lane == wl) {
+                int nw = 0;
+                unrank_product(c, u, [&](int r) { c.win[nw++] = (uint8_t)r; });
+                c.win[ORBG_ML_WINCAP] = (uint8_t)nw;
+            }
+            wave_lds_sync();
+            c.nwin = (int)uni32(c.win[ORBG_ML_WINCAP]);
+            return;
+        }
+    }
+    c.qbase += count;
+    if (c.qbase >= (uint64_t)c.budget) c.stop = true;
+}
+
+// Splits of `rest` over segments I..M-1 in the nested-loop order.
+template <int I, int M>
+__device__ void walk_splits(Walk<M>& c, int64_t rest)
+{
+    if constexpr (I == M - 1) {
+        const uint64_t n = seg_count(c.tbl, c.seg[I], rest);
+        if (n == 0) return;
+        c.a[I] = rest;
+        c.cnt[I] = n;
+        run_split<M>(c);
+    } else {
+        for (int64_t a = 0; a <= rest && !c.stop; a = seg_next(c.seg[I], a + 1)) {
+            c.a[I] = a;
+            c.cnt[I] = seg_count(c.tbl, c.seg[I], a);
+            walk_splits<I + 1, M>(c, rest - a);
+        }
+    }
+}
+
+// Smallest total weight >= need of segments I..M-1 that is below `bound`
+// (else `bound`).
+template <int I, int M>
+__device__ int64_t next_total(const Walk<M>& c, int64_t need, int64_t bound)
+{
+    if constexpr (I == M - 1) {
+        const int64_t v = seg_next(c.seg[I], need);
+        return v < bound ? v : bound;
+    } else {
+        int64_t best = bound;
+        for (int64_t a = 0; a < best; a = seg_next(c.seg[I], a + 1)) {
+            const int64_t r = next_total<I + 1, M>(c, need - a, best - a);
+            if (a + r < best) best = a + r;
+        }
+        return best;
+    }
+}
+
+template <int M>
+__device__ void walk(Walk<M>& c)
+{
+    int64_t W = 0;
+    for (;;) {
+        walk_splits<0, M>(c, W);
+        if (c.stop) return;
+        const int64_t nxt = next_total<0, M>(c, W + 1, NONE);
+        if (nxt == NONE) return;            // every pattern tested: abandoned
+        W = uni64(nxt);
+    }
+}
+
+__device__ __forceinline__ bool round_half_up(float x, int64_t& out)
+{
+    if (!__builtin_isfinite(x)) return false;
+    float r = floorf(__fadd_rn(x, 0.5f));
+    if (r > 1048576.0f) r = 1048576.0f;
+    out = (int64_t)r;
+    return true;
+}
+
+// LDS of one wave.
+struct MlLds {
+    uint64_t h[ORBG_ML_LMAX + 1];       // h[r] = column of rank r
+    float L[ORBG_ML_LMAX + 1];          // L[r] = |LLR| of rank r
+    uint16_t pi[ORBG_ML_LMAX + 1];      // pi[r] = received index of rank r
+    int anc[ORBG_ML_MSEG + 2];          // anchor ranks, ascending
+    uint8_t win[ORBG_ML_WINCAP + 1];    // winner's ranks, then their count
+};
+
+struct Model {
+    int m;
+    int I[ORBG_ML_MSEG + 1];
+    int64_t J[ORBG_ML_MSEG], B[ORBG_ML_MSEG];
+};
+
+__device__ __forceinline__ void model_basic(Model& md, int n)
+{
+    md.m = 1;
+    md.I[0] = 0;
+#pragma unroll
+    for (int i = 1; i <= ORBG_ML_MSEG; ++i) md.I[i] = n;
+#pragma unroll
+    for (int i = 0; i < ORBG_ML_MSEG; ++i) { md.J[i] = 0; md.B[i] = 1; }
+}
+
+// Fit with at most mreq segments (L in LDS, ranks 1..n).  Wave-uniform result.
+__device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
+{
+    const int lane = lane_id();
+    Model md;
+    model_basic(md, n);
+    const int h = n / 2;
+    if (h < 2) return md;
+    if (lane == 0) { S.anc[0] = 1; S.anc[1] = h; }
+    wave_lds_sync();
+    int na = 2;
+    for (int it = 1; it < mreq; ++it) {
+        // lane l: candidate rank j = l + 1 strictly between two adjacent anchors
+        const int j = lane + 1;
+        int a = 0, b = 0;
+        for (int p = 0; p + 1 < na; ++p) {
+            const int lo = S.anc[p], hi = S.anc[p + 1];
+            if (j > lo && j < hi) { a = lo; b = hi; }
+        }
+        bool ok = (b != 0) && j <= h;
+        float gap = 0.0f;
+        if (ok) {
+            const float La = S.L[a], Lb = S.L[b];
+            const float s = __fdiv_rn(__fsub_rn(Lb, La), (float)(b - a));
+            const float t = __fmul_rn((float)(j - a), s);
+            const float line = __fadd_rn(La, t);
+            gap = fabsf(__fsub_rn(S.L[j], line));
+            ok = !__builtin_isnan(gap);
+        }
+        // largest gap, smallest rank on ties: max of (gap bits, 255 - j)
+        uint64_t key = ok ? (((uint64_t)__float_as_uint(gap) << 32) | (uint64_t)(255 - j)) : 0ull;
+#pragma unroll
+        for (int d = 1; d < ORBG_WAVE; d <<= 1) {
+            const uint64_t o = __shfl_xor(key, d, ORBG_WAVE);
+            key = o > key ? o : key;
+        }
+        key = (uint64_t)uni64((int64_t)key);
+        if (key == 0ull) break;                                  // no rank left between anchors
+        if ((uint32_t)(key >> 32) == 0u) break;                  // largest gap is 0
+        const int bj = 255 - (int)(key & 0xffffffffull);
+        if (lane == 0) {
+            int p = na;
+            while (p > 0 && S.anc[p - 1] > bj) { S.anc[p] = S.anc[p - 1]; --p; }
+            S.anc[p] = bj;
+        }
+        wave_lds_sync();
+        ++na;
+    }
+    const int m = na - 1;
+    float d[ORBG_ML_MSEG], len[ORBG_ML_MSEG];
+    float Q = 0.0f;
+#pragma unroll
+    for (int i = 0; i < ORBG_ML_MSEG; ++i) {
+        if (i < m) {
+            const int lo = S.anc[i], hi = S.anc[i + 1];
+            d[i] = __fsub_rn(S.L[hi], S.L[lo]);
+            len[i] = (float)(hi - lo);
+            const float s = __fdiv_rn(d[i], len[i]);
+            if (i == 0 || s < Q) Q = s;
+        } else {
+            d[i] = 0.0f;
+            len[i] = 1.0f;
+        }
+    }
+    if (!(Q > 0.0f) || !__builtin_isfinite(Q)) return md;
+    Model r;
+    r.m = m;
+    r.I[0] = 0;
+#pragma unroll
+    for (int i = 1; i <= ORBG_ML_MSEG; ++i) r.I[i] = i < m ? S.anc[i] : n;
+#pragma unroll
+    for (int i = 0; i < ORBG_ML_MSEG; ++i) {
+        r.J[i] = 0;
+        r.B[i] = 1;
+        if (i < m) {
+            const float t = __fmul_rn(len[i], Q);
+            if (!round_half_up(__fdiv_rn(d[i], t), r.B[i]) || r.B[i] < 1) return md;
+        }
+    }
+    int64_t rb = 0;
+    if (!round_half_up(__fdiv_rn(S.L[1], Q), rb)) return md;
+    r.J[0] = rb - r.B[0];
+#pragma unroll
+    for (int i = 1; i < ORBG_ML_MSEG; ++i)
+        if (i < m && !round_half_up(__fdiv_rn(S.L[S.anc[i]], Q), r.J[i])) return md;
+    if (jdiv) {
+#pragma unroll
+        for (int i = 0; i < ORBG_ML_MSEG; ++i) {
+            const int64_t num = 2 * r.J[i] + r.B[i], den = 2 * r.B[i];
+            int64_t qq = num / den;
+            if (num % den != 0 && num < 0) --qq;
+            r.J[i] = qq * r.B[i];
+        }
+    }
+    return r;
+}
+
+template <int M>
+__device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint64_t s0, uint32_t budget,
+                            bool& found, uint32_t& q, int& nwin)
+{
+    Walk<M> c;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        c.seg[i].J = md.J[i];
+        c.seg[i].B = md.B[i];
+        c.seg[i].off = md.I[i];
+        c.seg[i].len = md.I[i + 1] - md.I[i];
+    }
+    c.qbase = 0;
+    c.budget = budget;
+    c.s0 = s0;
+    c.tbl = tbl;
+    c.h = S.h;
+    c.win = S.win;
+    c.nwin = 0;
+    c.stop = false;
+    c.found = false;
+    c.q = budget;
+    walk<M>(c);
+    found = c.found;
+    q = c.q;
+    nwin = c.nwin;
+}
+
+template <int NK>
+__global__ void __launch_bounds__(ORBG_WAVE) mline_kernel(MlineArgs a)
+{
+    __shared__ MlLds S;
+    const int lane = lane_id();
+    const int n = a.n;
+    // rows of H, one per lane (lanes >= n - k hold zeros)
+    uint64_t hrow[NK];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) hrow[j] = lane < a.m ? a.rows[lane * NK + j] : 0ull;
+    for (int64_t b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
+        const float* row = a.llr + b * (int64_t)n;
+        float x[NK];
+        bool ybit[NK];
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+            const int i = j * ORBG_WAVE + lane;
+            x[j] = i < n ? row[i] : 0.0f;
+            ybit[j] = i < n && x[j] > 0.0f;
+            const uint64_t y = ballot(ybit[j]);
+            acc += __popcll(hrow[j] & y);
+        }
+        const uint64_t s0 = uniform_u64(ballot((acc & 1u) != 0u));
+        bool found = false;
+        uint32_t q = a.budget;
+        int nwin = 0;
+        int m_used = 1;
+        if (s0 != 0 || a.mfit != nullptr) {
+            // full reliability order, exact keys
+            uint64_t key[NK];
+#pragma unroll
+            for (int j = 0; j < NK; ++j) {
+                const int i = j * ORBG_WAVE + lane;
+                key[j] = i < n ? (((uint64_t)(__float_as_uint(x[j]) & 0x7fffffffu) << 32) | (uint32_t)i) : ~0ull;
+            }
+            bitonic_sort<NK>(key);
+#pragma unroll
+            for (int j = 0; j < NK; ++j) {
+                const int e = lane * NK + j;          // rank e + 1
+                if (e < n) {
+                    const uint32_t idx = (uint32_t)key[j];
+                    S.pi[e + 1] = (uint16_t)idx;
+                    S.h[e + 1] = a.cols[idx];
+                    S.L[e + 1] = __uint_as_float((uint32_t)(key[j] >> 32));
+                }
+            }
+            wave_lds_sync();
+            const Model md = fit_model(S, n, a.mseg, a.jdiv);
+            m_used = md.m;
+            if (s0 == 0) {
+                found = true;
+                q = 1;
+            } else {
+                switch (md.m) {
+                case 1: decode_walk<1>(md, a.table, S, s0, a.budget, found, q, nwin); break;
+                case 2: decode_walk<2>(md, a.table, S, s0, a.budget, found, q, nwin); break;
+                case 3: decode_walk<3>(md, a.table, S, s0, a.budget, found, q, nwin); break;
+                default: decode_walk<4>(md, a.table, S, s0, a.budget, found, q, nwin); break;
+                }
+            }
+        } else {
+            found = true;
+            q = 1;
+        }
+        // codeword: hard decision, the winner's ranks flipped
+        bool bit[NK];
+#pragma unroll
+        for (int j = 0; j < NK; ++j) bit[j] = ybit[j];
+        if (found) {
+            for (int k = 0; k < nwin; ++k) {
+                const uint32_t p = uni32(S.pi[S.win[k]]);
+#pragma unroll
+                for (int j = 0; j < NK; ++j)
+                    if ((p >> 6) == (uint32_t)j) bit[j] ^= (uint32_t)lane == (p & 63u);
+            }
+        }
+        uint8_t* cw = a.cw + b * (int64_t)n;
+#pragma unroll
+        for (int j = 0; j < NK; ++j) {
+            const int i = j * ORBG_WAVE + lane;
+            if (i < n) cw[i] = bit[j] ? 1 : 0;
+        }
+        if (lane == 0) {
+            a.queries[b] = found ? (uint64_t)q : (uint64_t)a.budget;
+            a.abandoned[b] = found ? 0 : 1;
+            if (a.mfit != nullptr) a.mfit[b] = m_used;
+        }
+        wave_lds_sync();
+    }
+}
+
+// One step of the subset-count recursion: table for `len` from the one for len - 1.
+__global__ void __launch_bounds__(256) subset_table_step(uint32_t* t, int len)
+{
+    const int cells = (WL + 1) * SL;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    uint32_t* cur = t + (size_t)len * cells;
+    if (len == 0) {
+        cur[c] = c == 0 ? 1u : 0u;
+        return;
+    }
+    const uint32_t* prev = t + (size_t)(len - 1) * cells;
+    const int w = c / SL, s = c % SL;
+    uint64_t v = prev[c];
+    if (w >= 1 && s >= len) v += prev[(w - 1) * SL + (s - len)];
+    cur[c] = v > 0xffffffffull ? 0xffffffffu : (uint32_t)v;
+}
+
+}  // namespace
+
+hipError_t build_subset_table(uint32_t* t, hipStream_t stream)
+{
+    const int cells = (WL + 1) * SL;
+    for (int len = 0; len <= ORBG_ML_LMAX; ++len) {
+        subset_table_step<<<(cells + 255) / 256, 256, 0, stream>>>(t, len);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_mline(const MlineArgs& a, int grid, hipStream_t stream)
+{
+    if (a.nblocks <= 0) return hipSuccess;
+    if (a.n <= ORBG_WAVE) mline_kernel<1><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    else mline_kernel<2><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace orbg

@@ -1,0 +1,38 @@
+// Full (m-line) ORBGRAND kernel interface (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ORBG_ML_WMAX 16          // flips per segment the order reaches within the budget limit
+#define ORBG_ML_SMAX 2048        // partial logistic weights 0..2047 (16 flips of ranks <= 128)
+#define ORBG_ML_LMAX 128         // largest code length (and segment length)
+#define ORBG_ML_MSEG 4           // largest number of segments
+#define ORBG_ML_WINCAP 64        // flips of one pattern: at most 16 per segment
+#define ORBG_ML_BUDGET_MAX 65536 // largest query budget (2^16)
+
+namespace orbg {
+
+struct MlineArgs {
+    const float* llr;          // nblocks x n
+    int n;
+    int m;                     // n - k
+    const uint64_t* cols;      // n packed parity-check columns
+    const uint64_t* rows;      // m x nk packed rows (nk = 1 for n <= 64, else 2)
+    int64_t nblocks;
+    uint32_t budget;
+    int mseg;                  // largest number of segments of the fit
+    bool jdiv;                 // J_{i-1} rounded to a multiple of beta_i
+    const uint32_t* table;     // subset counts, subset_table_words() entries
+    uint8_t* cw;
+    uint64_t* queries;
+    uint8_t* abandoned;
+    int32_t* mfit;             // per-block segment count, or nullptr
+};
+
+// Entries of the subset-count table: (LMAX + 1) x (WMAX + 1) x SMAX.
+constexpr size_t subset_table_words() { return (size_t)(ORBG_ML_LMAX + 1) * (ORBG_ML_WMAX + 1) * ORBG_ML_SMAX; }
+
+hipError_t build_subset_table(uint32_t* t, hipStream_t stream);
+hipError_t launch_mline(const MlineArgs& a, int grid, hipStream_t stream);
+
+}  // namespace orbg

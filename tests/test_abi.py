@@ -99,3 +99,23 @@ def test_1line_export_argument_errors(n, budget, j0, count, msg):
     rc = L.orbg_schedule_export_1line(n, budget, j0, count, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(jm),
                                       None)
     assert rc == -1 and msg in L.orbg_last_error().decode()
+
+
+@pytest.mark.parametrize("n,k,budget,seg,jdiv,bufs,msg", [
+    (0, 0, 10, 2, 0, True, "n = 0"),
+    (129, 120, 10, 2, 0, True, "n = 129"),
+    (100, 30, 10, 2, 0, True, "n - k = 70"),
+    (32, 26, 10, 0, 0, True, "segments = 0"),
+    (32, 26, 10, 5, 0, True, "segments = 5"),
+    (32, 26, 10, 2, 2, True, "jdiv = 2"),
+    (32, 26, 0, 2, 0, True, "budget = 0"),
+    (32, 26, 65537, 2, 0, True, "budget = 65537"),
+    (32, 26, 100, 2, 0, False, "device buffer is NULL"),
+])
+def test_mline_argument_errors(n, k, budget, seg, jdiv, bufs, msg):
+    L = binding.load()
+    m = max(n - k, 1)
+    H = np.zeros((m, max(n, 1)), dtype=np.uint8)
+    p = ctypes.c_void_p(8) if bufs else None
+    rc = L.orbg_decode_mline(H.ctypes.data_as(ctypes.c_void_p), p, n, k, budget, 4, seg, jdiv, p, p, p, None, None)
+    assert rc == -1 and msg in L.orbg_last_error().decode()

@@ -1,0 +1,174 @@
+"""GPU parity of full (m-line) ORBGRAND (Sec. IV): the HIP decoder against the
+oracle decoder bit for bit -- codeword, query count, abandon flag and the number
+of segments the fit used -- on the same seeded inputs, for one to four segments,
+with and without the J/beta rounding."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2202_13951_amd import binding
+from synth import channel, codes
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _gpu(H, llr, budget, segments, jdiv, dev, report=True):
+    cw, q, ab, ms = binding.orbg_decode_mline(H, torch.from_numpy(np.ascontiguousarray(llr)).to(dev), budget,
+                                              segments, jdiv, segments_out=report)
+    torch.cuda.synchronize()
+    return (cw.cpu().numpy(), q.cpu().numpy().astype(np.uint64), ab.cpu().numpy(),
+            None if ms is None else ms.cpu().numpy())
+
+
+def _oracle(H, llr, budget, segments, jdiv):
+    return O.decode_mline(H, llr, budget, segments, jdiv, THREADS)
+
+
+def _assert_same(got, want, tag="", check_m=True):
+    gcw, gq, gab, gm = got
+    ocw, oq, oab, om = want
+    diff = (gcw != ocw).any(axis=1) | (gq != oq) | (gab != oab)
+    if check_m:
+        diff |= gm != om
+    bad = np.nonzero(diff)[0]
+    assert bad.size == 0, (f"{tag}: {bad.size} blocks differ, first {bad[:8].tolist()}: gpu q={gq[bad[:4]].tolist()} "
+                           f"oracle q={oq[bad[:4]].tolist()} gpu m={None if gm is None else gm[bad[:4]].tolist()} "
+                           f"oracle m={om[bad[:4]].tolist()}")
+
+
+def _both(H, llr, budget, segments, jdiv, dev, tag):
+    print(f"m-line {tag} segments={segments} jdiv={jdiv} budget={budget}", flush=True)
+    want = _oracle(H, llr, budget, segments, jdiv)
+    _assert_same(_gpu(H, llr, budget, segments, jdiv, dev), want, tag)
+    _assert_same(_gpu(H, llr, budget, segments, jdiv, dev, report=None), want, tag + " no m", check_m=False)
+    return want
+
+
+@pytest.mark.parametrize("segments", [1, 2, 3, 4])
+@pytest.mark.parametrize("jdiv", [False, True])
+def test_rlc32_26(gpu_device, segments, jdiv):
+    H, G = codes.code("rlc32_26")
+    llr, _ = channel.awgn_llr(G, 5000, 3.0, seed=301)
+    want = _both(H, llr, 5000, segments, jdiv, gpu_device, "rlc32")
+    assert want[3].max() == min(segments, 4)
+
+
+@pytest.mark.parametrize("ebn0", [4.0, 5.5, 7.0])
+@pytest.mark.parametrize("segments", [2, 3, 4])
+def test_bch127_113(gpu_device, ebn0, segments):
+    H, G = codes.code("bch127_113")
+    llr, _ = channel.awgn_llr(G, 2000, ebn0, seed=int(ebn0 * 10) + 700)
+    want = _both(H, llr, 10 ** 4, segments, False, gpu_device, f"bch127 {ebn0} dB")
+    assert want[3].max() == segments
+
+
+def test_one_segment_is_the_1line_decoder(gpu_device):
+    """One segment: the m-line kernel and the 1-line kernel (precomputed schedules)
+    give the same results, and both equal the 1-line oracle."""
+    print("m-line one segment vs 1-line", flush=True)
+    H, G = codes.code("bch127_113")
+    llr, _ = channel.awgn_llr(G, 3000, 4.5, seed=77)
+    one = O.decode_1line(H, llr, 20000, THREADS)
+    got = _gpu(H, llr, 20000, 1, False, gpu_device)
+    assert (got[0] == one[0]).all() and (got[1] == one[1]).all() and (got[2] == one[2]).all()
+    cw, q, ab, _ = binding.orbg_decode_1line(H, torch.from_numpy(llr).to(gpu_device), 20000, j0=None)
+    torch.cuda.synchronize()
+    assert (cw.cpu().numpy() == got[0]).all() and (q.cpu().numpy().astype(np.uint64) == got[1]).all()
+
+
+@pytest.mark.parametrize("n,k,budget,ebn0,segments,jdiv", [
+    (4, 2, 16, 1.0, 3, False), (8, 3, 2 ** 8, 1.0, 2, False), (12, 5, 2 ** 12, 1.5, 3, True),
+    (33, 20, 30000, 2.0, 4, False), (63, 50, 20000, 2.5, 3, False), (64, 40, 65536, 2.0, 2, True),
+    (65, 52, 20000, 2.5, 4, False), (100, 36, 3000, 2.5, 3, False), (128, 80, 5000, 3.0, 4, True),
+    (128, 64, 2000, 3.0, 2, False)])
+def test_ragged_lengths(gpu_device, n, k, budget, ebn0, segments, jdiv):
+    """Ragged lengths with one and two keys per lane, n - k up to 64, budgets up to 2^16."""
+    H = codes.rlc_H(n, k, seed=n * 7 + k)
+    G = codes.generator_matrix(H)
+    llr, _ = channel.awgn_llr(G, 300, ebn0, seed=n + 5 * k)
+    _both(H, llr, budget, segments, jdiv, gpu_device, f"n={n} k={k}")
+
+
+def test_special_values_and_fit_edges(gpu_device):
+    """Zero, NaN and infinite LLRs, ties, constant magnitudes, exact piecewise-linear
+    curves (anchors at the corners, roundings on halves), large offsets and slopes,
+    and codewords (q = 1)."""
+    H, G = codes.code("rlc64_52")
+    rng = np.random.default_rng(13)
+    llr = rng.standard_normal((120, 64)).astype(np.float32)
+    llr[0] = 0.0
+    llr[1] = -0.0
+    llr[2] = 0.75
+    llr[3, ::3] = np.nan
+    llr[4, :40] = np.inf
+    llr[5, :10] = -np.inf
+    llr[6] = np.round(llr[6])
+    llr[7:15] = np.round(llr[7:15] * 4) / 4
+
+    def place(b, mags):
+        mags = np.asarray(mags, dtype=np.float32)
+        llr[b] = (rng.permutation(mags) * rng.choice([-1, 1], 64)).astype(np.float32)
+    for b in range(15, 30):                                   # two or three exact lines
+        c1, c2 = int(rng.integers(3, 12)), int(rng.integers(14, 30))
+        s1, s2, s3 = 0.5 * rng.integers(1, 4), 0.5 * rng.integers(4, 8), 0.5 * rng.integers(8, 16)
+        off = 0.25 * rng.integers(0, 8)
+        L = []
+        for j in range(1, 65):
+            v = off + s1 * min(j, c1)
+            v += s2 * max(0, min(j, c2) - c1)
+            v += s3 * max(0, j - c2)
+            L.append(v)
+        place(b, L)
+    for b in range(30, 45):                                   # large offsets, small slopes
+        off, slope = 10.0 ** rng.uniform(0, 3), 10.0 ** rng.uniform(-4, 0)
+        place(b, off + slope * np.arange(1, 65) + 0.3 * slope * np.arange(1, 65) ** 1.5)
+    for b in range(45, 55):                                   # a flat start: zero slope
+        place(b, np.concatenate([np.full(int(rng.integers(3, 20)), 1.0), 2.0 + np.arange(64)])[:64])
+    book = channel.encode(G, rng.integers(0, 2, (8, 52), dtype=np.uint8))
+    llr[55:63] = (2.0 * book - 1.0) * 5.0
+    for segments in (2, 3, 4):
+        for jdiv in (False, True):
+            want = _both(H, llr, 5000, segments, jdiv, gpu_device, "special")
+    assert want[3].max() == 4 and want[3].min() == 1
+
+
+def test_budget_edges(gpu_device):
+    H = codes.rlc_H(40, 20, seed=6)
+    rng = np.random.default_rng(9)
+    llr = rng.standard_normal((200, 40)).astype(np.float32)
+    for budget in (1, 2, 63, 64, 65, 127, 4097, 65536):
+        want = _both(H, llr, budget, 3, False, gpu_device, "budget edges")
+    assert want[2].sum() > 0
+
+
+def test_empty_batch(gpu_device):
+    H, _ = codes.code("rlc32_26")
+    llr = torch.empty((0, 32), dtype=torch.float32, device=gpu_device)
+    cw, q, ab, ms = binding.orbg_decode_mline(H, llr, 100, 3)
+    torch.cuda.synchronize()
+    assert cw.shape == (0, 32) and ms.shape == (0,)
+    H256, _ = codes.code("rlc256_240")
+    with pytest.raises(binding.OrbgError):                    # n above 128
+        binding.orbg_decode_mline(H256, torch.zeros((4, 256), dtype=torch.float32, device=gpu_device), 100, 2)
+
+
+def test_bch_full_size_sampled(gpu_device):
+    """BCH(127,113), 10^6 blocks at 5 dB, two segments, budget 10^4, one launch:
+    sampled blocks against the oracle, and properties of every block."""
+    print("m-line bch127 full size", flush=True)
+    H, G = codes.code("bch127_113")
+    N = 10 ** 6
+    llr, _ = channel.awgn_llr(G, N, 5.0, seed=4242)
+    cw, q, ab, ms = _gpu(H, llr, 10 ** 4, 2, False, gpu_device)
+    idx = np.random.default_rng(3).choice(N, 4000, replace=False)
+    want = _oracle(H, llr[idx], 10 ** 4, 2, False)
+    _assert_same((cw[idx], q[idx], ab[idx], ms[idx]), want, "full size sample")
+    assert ((q >= 1) & (q <= 10 ** 4)).all() and (q[ab == 1] == 10 ** 4).all()
+    assert set(np.unique(ms).tolist()) <= {1, 2}
+    ok = np.nonzero(ab == 0)[0][:2000]
+    syn = (cw[ok].astype(np.int64) @ H.T.astype(np.int64)) % 2
+    assert not syn.any()
