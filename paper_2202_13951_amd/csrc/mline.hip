@@ -73,13 +73,16 @@ struct Seg {
 
 __device__ __forceinline__ int wcap(const Seg& g) { return g.len < WL ? g.len : WL; }
 
-// Relative logistic weight of w >= 1 flips with partial weight x, or -1.
+// Relative logistic weight of w >= 1 flips with partial weight x, or -1.  The
+// range test comes first, so the one division left has operands below 2^32
+// (relative weights <= 1928, slopes <= 2^20).
 __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
 {
     const int64_t r = x - (int64_t)w * g.J;
-    if (r < 0 || r % g.B != 0) return -1;
-    const int64_t wp = r / g.B;
-    return (wp < lw_min(w) || wp > lw_max(w, g.len)) ? -1 : wp;
+    if (r < lw_min(w) * g.B || r > lw_max(w, g.len) * g.B) return -1;
+    if (g.B == 1) return r;
+    const uint32_t rr = (uint32_t)r, bb = (uint32_t)g.B, wp = rr / bb;
+    return wp * bb == rr ? (int64_t)wp : -1;
 }
 
 // Number of partial patterns (at most 16 flips) of the segment with partial
@@ -103,13 +106,39 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
     const int wc = wcap(g);
     for (int w = 1; w <= wc; ++w) {
         const int64_t lo = lw_min(w), hi = lw_max(w, g.len), need = x - (int64_t)w * g.J;
-        int64_t wp = need <= 0 ? lo : (need + g.B - 1) / g.B;
-        if (wp < lo) wp = lo;
-        if (wp > hi) continue;
+        int64_t wp;
+        if (need <= lo * g.B) {
+            wp = lo;                                   // ceil(need / B) <= lo
+        } else if (need > hi * g.B) {
+            continue;                                  // ceil(need / B) > hi
+        } else {
+            const uint32_t nn = (uint32_t)need, bb = (uint32_t)g.B;
+            wp = g.B == 1 ? need : (int64_t)((nn + bb - 1u) / bb);
+        }
         const int64_t c = (int64_t)w * g.J + g.B * wp;
         if (c < best) best = c;
     }
     return best;
+}
+
+// Can the segment take partial weight x (some partial Hamming weight <= 16)?
+__device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
+{
+    if (x == 0) return true;
+    const int wc = wcap(g);
+    bool ok = false;
+    for (int w = 1; w <= wc; ++w) ok |= rel_weight(g, x, w) >= 0;
+    return ok;
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+#pragma unroll
+    for (int d = 1; d < ORBG_WAVE; d <<= 1) {
+        const int64_t o = __shfl_xor(v, d, ORBG_WAVE);
+        v = o < v ? o : v;
+    }
+    return uni64(v);
 }
 
 template <int M>
@@ -179,11 +208,19 @@ __device__ __forceinline__ void unrank_partial(const uint32_t* __restrict__ tbl,
 template <int M, typename F>
 __device__ __forceinline__ void unrank_product(const Walk<M>& c, uint64_t u, F&& emit)
 {
+    // u < 2^16: a radix above u leaves the digit u and quotient 0, smaller ones
+    // fit 32-bit division
     uint64_t t[M];
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
-        t[i] = (i == 0) ? u : u % c.cnt[i];
-        u = (i == 0) ? 0 : u / c.cnt[i];
+        if (i == 0 || c.cnt[i] > u) {
+            t[i] = u;
+            u = 0;
+        } else {
+            const uint32_t uu = (uint32_t)u, rr = (uint32_t)c.cnt[i];
+            t[i] = uu % rr;
+            u = uu / rr;
+        }
     }
 #pragma unroll
     for (int i = 0; i < M; ++i) unrank_partial(c.tbl, c.seg[i], c.a[i], t[i], emit);
@@ -232,7 +269,11 @@ __device__ void run_split(Walk<M>& c)
     if (c.qbase >= (uint64_t)c.budget) c.stop = true;
 }
 
-// Splits of `rest` over segments I..M-1 in the nested-loop order.
+// Splits of `rest` over segments I..M-1 in the nested-loop order.  The last two
+// segments are searched 64 candidate values of W_{M-1} at a time (lane l takes
+// base + l; a ballot keeps those both segments can take, taken in ascending
+// order), and a stretch without candidates is skipped to the next value
+// segment M-2 can take.
 template <int I, int M>
 __device__ void walk_splits(Walk<M>& c, int64_t rest)
 {
@@ -242,6 +283,21 @@ __device__ void walk_splits(Walk<M>& c, int64_t rest)
         c.a[I] = rest;
         c.cnt[I] = n;
         run_split<M>(c);
+    } else if constexpr (I == M - 2) {
+        const int lane = lane_id();
+        for (int64_t base = 0; base <= rest && !c.stop;) {
+            const int64_t a = base + lane;
+            const bool ok = a <= rest && seg_member(c.seg[I], a) && seg_member(c.seg[I + 1], rest - a);
+            for (uint64_t bal = ballot(ok); bal != 0 && !c.stop; bal &= bal - 1) {
+                const int64_t av = base + (int64_t)__builtin_ctzll(bal);
+                c.a[I] = av;
+                c.cnt[I] = seg_count(c.tbl, c.seg[I], av);
+                c.a[I + 1] = rest - av;
+                c.cnt[I + 1] = seg_count(c.tbl, c.seg[I + 1], rest - av);
+                run_split<M>(c);
+            }
+            base = seg_next(c.seg[I], base + ORBG_WAVE);
+        }
     } else {
         for (int64_t a = 0; a <= rest && !c.stop; a = seg_next(c.seg[I], a + 1)) {
             c.a[I] = a;
@@ -252,13 +308,32 @@ __device__ void walk_splits(Walk<M>& c, int64_t rest)
 }
 
 // Smallest total weight >= need of segments I..M-1 that is below `bound`
-// (else `bound`).
+// (else `bound`).  For the last two segments: a value a of segment M-2 at or
+// above `need` stands alone (the last segment adds 0), the smallest such is
+// its next value; below `need` the lanes take 64 candidates a at a time, each
+// adding the last segment's next value at or above need - a.
 template <int I, int M>
 __device__ int64_t next_total(const Walk<M>& c, int64_t need, int64_t bound)
 {
     if constexpr (I == M - 1) {
         const int64_t v = seg_next(c.seg[I], need);
         return v < bound ? v : bound;
+    } else if constexpr (I == M - 2) {
+        int64_t best = seg_next(c.seg[I], need);
+        best = best < bound ? best : bound;
+        const int lane = lane_id();
+        for (int64_t base = 0; base < need && base < best;) {
+            const int64_t a = base + lane;
+            int64_t cand = NONE;
+            if (a < need && a < best && seg_member(c.seg[I], a)) {
+                const int64_t r = seg_next(c.seg[I + 1], need - a);
+                if (r != NONE) cand = a + r;
+            }
+            const int64_t m = wave_min_i64(cand);
+            best = m < best ? m : best;
+            base = seg_next(c.seg[I], base + ORBG_WAVE);
+        }
+        return best;
     } else {
         int64_t best = bound;
         for (int64_t a = 0; a < best; a = seg_next(c.seg[I], a + 1)) {
