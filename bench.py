@@ -52,6 +52,11 @@ WORKLOADS = {
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
                               "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. IV) against basic ORBGRAND "
                               "on the same blocks"),
+    "bch127_mline": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
+                         blocks=10 ** 6, budget=65536, mline=True, segments=2,
+                         desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
+                              "budget 2^16, full ORBGRAND with a 2-line fit (Sec. IV) against its J/beta variant, "
+                              "1-line and basic ORBGRAND on the same blocks"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
     "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),
@@ -149,14 +154,18 @@ def query_breakdown(q, ab, err, budget, sweep=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 
     return out
 
 
+# Sources the basic and 1-line decode kernels (light and heavy pass, schedules,
+# launch) are compiled from: their HBM counters stay valid while these are unchanged.
+DECODE_SOURCES = ("decode.hip", "orbg_device.h", "orbg_internal.h", "orbg_kernels.h", "schedule.hip")
+
+
 def kernel_fingerprint() -> str:
-    """sha256 (first 16 hex digits) over the names and contents of the kernel sources."""
-    import glob
+    """sha256 (first 16 hex digits) over the names and contents of the decode kernels' sources."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_13951_amd", "csrc", "*"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in DECODE_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2202_13951_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -178,14 +187,15 @@ def profiled_traffic(workload: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0, oneline=False):
+def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0, oneline=False, dec=None):
     """Times the oracle (as it stands) on the first blocks of every Eb/N0 point.
     rows(p, count) -> host float32 [count, n], the first `count` rows of point p.
     A first pass on 2000 blocks per point sizes the sample (that pass overstates the
     per-block cost, so the timed sample lasts about half of target_s).  oneline: the
-    oracle's 1-line decoder."""
+    oracle's 1-line decoder; dec(H, x, budget, threads) replaces the decoder."""
     from oracle import oracle as O
-    dec = O.decode_1line if oneline else O.decode
+    if dec is None:
+        dec = O.decode_1line if oneline else O.decode
     threads = len(os.sched_getaffinity(0))
     per = min(2000, per_max)
     xs = [rows(p, per) for p in range(npoints)]
@@ -781,6 +791,129 @@ def run_learned(args, wl, dev):
     }
 
 
+def run_mline(args, wl, dev):
+    """Full m-line ORBGRAND over all points in one call per step (timed), then per
+    point: BLER, queries and the segment counts of the fit, the same with the J/beta
+    rounding, and the 1-line and basic decoders on the same blocks at the same
+    budget, each timed on its own."""
+    import torch
+    from paper_2202_13951_amd import binding
+    H, llr, sent = single_inputs(wl, dev)
+    n, budget = wl["n"], wl["budget"]
+    segments = args.segments if args.segments else wl["segments"]
+    P, B = len(wl["ebn0"]), wl["blocks"]
+    cw = torch.empty_like(sent)
+    q = torch.empty((P * B,), dtype=torch.int64, device=dev)
+    ab = torch.empty((P * B,), dtype=torch.uint8, device=dev)
+    out = (cw, q, ab)
+    stream = torch.cuda.current_stream()
+
+    def one():
+        binding.orbg_decode_mline(H, llr, budget, segments, segments_out=False, out=out)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        one()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        one()
+        ev[i][1].record(stream)
+        print(f"step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    blocks = P * B
+    q_np = q.cpu().numpy()
+    ab_np = ab.cpu().numpy()
+    err = (cw != sent).any(dim=1).cpu().numpy()
+    per_point = {}
+    if not args.no_per_point:
+        ms = torch.empty((B,), dtype=torch.int32, device=dev)
+        ocw = torch.empty((B, n), dtype=torch.uint8, device=dev)
+        oq = torch.empty((B,), dtype=torch.int64, device=dev)
+        oab = torch.empty((B,), dtype=torch.uint8, device=dev)
+
+        def other(fn, sl):
+            t = time_calls(lambda: fn(sl), stream, reps=1) / 1e3
+            e_ = (ocw != sent[sl]).any(dim=1).cpu().numpy()
+            qq = oq.cpu().numpy()
+            ne_ = int(e_.sum())
+            return {"bler": ne_ / B, "errors": ne_, "bler_ci95": list(wilson(ne_, B)),
+                    "mean_queries": float(qq.mean()), "abandoned": int(oab.sum().item()), "blocks_per_s": B / t}, e_
+        binding.orbg_decode_ex(H, llr[:B], budget, out=(ocw, oq, oab))             # builds the schedules
+        binding.orbg_decode_1line(H, llr[:B], budget, j0=False, out=(ocw, oq, oab))
+        torch.cuda.synchronize()
+        for p, e in enumerate(wl["ebn0"]):
+            sl = slice(p * B, (p + 1) * B)
+            print(f"point {e} dB", file=sys.stderr, flush=True)
+            ne = int(err[sl].sum())
+            binding.orbg_decode_mline(H, llr[sl], budget, segments, segments_out=ms, out=(ocw, oq, oab))
+            torch.cuda.synchronize()
+            same = bool((ocw == cw[sl]).all().item() and (oq == q[sl]).all().item())
+            vals, cnts = np.unique(ms.cpu().numpy(), return_counts=True)
+            t = time_calls(lambda: binding.orbg_decode_mline(H, llr[sl], budget, segments, segments_out=False,
+                                                              out=(ocw, oq, oab)), stream, reps=1) / 1e3
+            pt = {"bler": ne / B, "errors": ne, "bler_ci95": list(wilson(ne, B)),
+                  "mean_queries": float(q_np[sl].mean()), "abandoned": int(ab_np[sl].sum()),
+                  "breakdown": query_breakdown(q_np[sl], ab_np[sl], err[sl], budget,
+                                               sweep=(10 ** 2, 10 ** 3, 10 ** 4, 65536)),
+                  "segments_used": {str(int(v)): float(c / B) for v, c in zip(vals, cnts)},
+                  "segments_call_identical": same,
+                  "blocks_per_s": B / t, "queries_per_s": float(q_np[sl].sum()) / t}
+            pt["jbeta"], _ = other(lambda s_: binding.orbg_decode_mline(H, llr[s_], budget, segments, jdiv=True,
+                                                                        segments_out=False, out=(ocw, oq, oab)), sl)
+            pt["one_line"], e1 = other(lambda s_: binding.orbg_decode_1line(H, llr[s_], budget, j0=False,
+                                                                            out=(ocw, oq, oab)), sl)
+            pt["basic"], eb = other(lambda s_: binding.orbg_decode_ex(H, llr[s_], budget, out=(ocw, oq, oab)), sl)
+            pt["only_mline_correct_vs_basic"] = int((~err[sl] & eb).sum())
+            pt["only_basic_correct"] = int((err[sl] & ~eb).sum())
+            per_point[f"{e:.1f}"] = pt
+
+    kavg = float(np.mean(kern_ms)) / 1e3
+    q_sum = int(q_np.sum())
+    n_sorted = int((q_np > 1).sum())
+    ops = algorithmic_ops(q_sum, n_sorted, n)
+    hbm_bytes = blocks * (4 * n + n + 8 + 1)
+    result = {
+        "metric": METRIC,
+        "value": blocks / (wall / args.steps),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"] if segments == wl["segments"] else
+                   wl["desc"].replace("a 2-line fit", f"a fit of at most {segments} lines"),
+                   "code": wl["code"], "n": n, "k": wl["k"], "ebn0_db": wl["ebn0"],
+                   "blocks_per_step": blocks, "budget": budget, "segments": segments},
+        "queries_per_s": q_sum / (wall / args.steps),
+        "mean_queries": q_sum / blocks,
+        "kernel_ms": float(np.mean(kern_ms)),
+        "per_point": per_point,
+        "roofline": {"bound": "alu", "achieved": ops / kavg / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS, "traffic": None,
+                     "kernel": "mline_kernel (one decode call)", "ops_per_launch": ops,
+                     "hbm": {"achieved_GBps": hbm_bytes / kavg / 1e9, "peak_GBps": PEAK_HBM / 1e9,
+                             "frac": hbm_bytes / kavg / PEAK_HBM, "bytes_per_launch": hbm_bytes}},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        result["cpu_baseline"] = cpu_baseline(H, lambda p, c: llr[p * B:p * B + c].cpu().numpy(), P, B, budget,
+                                              dec=lambda H_, x, b_, th: O.decode_mline(H_, x, b_, segments, False,
+                                                                                       th))
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -791,6 +924,7 @@ def main():
     ap.add_argument("--no-per-point", action="store_true",
                     help="skip the per-Eb/N0 launches (profiling runs: only the timed launches remain)")
     ap.add_argument("--no-tuned", action="store_true", help="library default launch shape")
+    ap.add_argument("--segments", type=int, default=0, help="m-line workload: largest number of segments (1..4)")
     ap.add_argument("--ebn0", type=float, nargs="*", default=None,
                     help="decode only these Eb/N0 points of the workload (diagnosis runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -819,6 +953,8 @@ def main():
         result = run_learned(args, wl, dev)
     elif wl.get("oneline"):
         result = run_oneline(args, wl, dev)
+    elif wl.get("mline"):
+        result = run_mline(args, wl, dev)
     else:
         result = run_single(args, wl, dev)
     if args.ebn0 and "roofline" in result:
