@@ -85,13 +85,18 @@ __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
     return wp * bb == rr ? (int64_t)wp : -1;
 }
 
+// Smallest partial weight of w flips: w J + beta w(w+1)/2.  It grows strictly
+// with w (by J + beta (w+1) >= beta w > 0, as J >= -beta), so the loops over w
+// below stop at the first w whose smallest weight passes x.
+__device__ __forceinline__ int64_t min_weight(const Seg& g, int w) { return (int64_t)w * g.J + g.B * lw_min(w); }
+
 // Number of partial patterns (at most 16 flips) of the segment with partial
 // weight x; the empty one has weight 0.
 __device__ uint64_t seg_count(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x)
 {
     uint64_t c = x == 0 ? 1u : 0u;
     const int wc = wcap(g);
-    for (int w = 1; w <= wc; ++w) {
+    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w) {
         const int64_t wp = rel_weight(g, x, w);
         if (wp >= 0) c += subset_count(tbl, g.len, w, wp);
     }
@@ -108,7 +113,10 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
         const int64_t lo = lw_min(w), hi = lw_max(w, g.len), need = x - (int64_t)w * g.J;
         int64_t wp;
         if (need <= lo * g.B) {
-            wp = lo;                                   // ceil(need / B) <= lo
+            // the smallest weight of w flips is >= x; larger w only give more
+            const int64_t c = min_weight(g, w);
+            if (c < best) best = c;
+            break;
         } else if (need > hi * g.B) {
             continue;                                  // ceil(need / B) > hi
         } else {
@@ -126,9 +134,9 @@ __device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
 {
     if (x == 0) return true;
     const int wc = wcap(g);
-    bool ok = false;
-    for (int w = 1; w <= wc; ++w) ok |= rel_weight(g, x, w) >= 0;
-    return ok;
+    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w)
+        if (rel_weight(g, x, w) >= 0) return true;
+    return false;
 }
 
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
@@ -192,7 +200,7 @@ __device__ __forceinline__ void unrank_partial(const uint32_t* __restrict__ tbl,
         u -= 1;
     }
     const int wc = wcap(g);
-    for (int w = 1; w <= wc; ++w) {
+    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w) {
         const int64_t wp = rel_weight(g, x, w);
         if (wp < 0) continue;
         const uint64_t n = subset_count(tbl, g.len, w, wp);
