@@ -149,17 +149,31 @@ __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
     return uni64(v);
 }
 
+// A split waiting to be tested (LDS ring of ORBG_ML_QCAP entries): its partial
+// weights, partial-set sizes (saturated at 2^32 - 1, exact for product indices
+// below 2^16), the first product element not yet tested and the number of
+// elements to test (the product size, cut at the budget).
+struct QEntry {
+    int64_t a[ORBG_ML_MSEG];
+    uint32_t cnt[ORBG_ML_MSEG];
+    uint32_t first, total;
+};
+
 template <int M>
 struct Walk {
     Seg seg[M];
     int64_t a[M];           // current split
     uint64_t cnt[M];        // partial-set sizes of the split
-    uint64_t qbase;         // patterns tested before the current split
+    uint64_t qbase;         // patterns tested
+    uint32_t pending;       // patterns queued, not yet tested
+    uint32_t want;          // queued patterns that start a test: 2, doubling to 64
+    int qhead, live;        // ring position and number of queued splits
     uint32_t budget;
     uint64_t s0;
     const uint32_t* tbl;
     const uint64_t* h;      // LDS: column of each rank
     uint8_t* win;           // LDS: the winner's ranks
+    QEntry* Q;              // LDS: queued splits
     int nwin;
     bool stop, found;
     uint32_t q;
@@ -212,26 +226,26 @@ __device__ __forceinline__ void unrank_partial(const uint32_t* __restrict__ tbl,
     }
 }
 
-// Product element u of the current split, segment 1 outermost.
+// Product element u of a split (partial weights a, partial-set sizes cnt),
+// segment 1 outermost.
 template <int M, typename F>
-__device__ __forceinline__ void unrank_product(const Walk<M>& c, uint64_t u, F&& emit)
+__device__ __forceinline__ void unrank_product(const Seg (&seg)[M], const uint32_t* tbl, const int64_t (&a)[M],
+                                               const uint32_t (&cnt)[M], uint32_t u, F&& emit)
 {
-    // u < 2^16: a radix above u leaves the digit u and quotient 0, smaller ones
-    // fit 32-bit division
-    uint64_t t[M];
+    // u < 2^16: a radix above u leaves the digit u and quotient 0
+    uint32_t t[M];
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
-        if (i == 0 || c.cnt[i] > u) {
+        if (i == 0 || cnt[i] > u) {
             t[i] = u;
             u = 0;
         } else {
-            const uint32_t uu = (uint32_t)u, rr = (uint32_t)c.cnt[i];
-            t[i] = uu % rr;
-            u = uu / rr;
+            t[i] = u % cnt[i];
+            u = u / cnt[i];
         }
     }
 #pragma unroll
-    for (int i = 0; i < M; ++i) unrank_partial(c.tbl, c.seg[i], c.a[i], t[i], emit);
+    for (int i = 0; i < M; ++i) unrank_partial(tbl, seg[i], a[i], t[i], emit);
 }
 
 __device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b)
@@ -242,39 +256,106 @@ __device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b)
     return a * b;
 }
 
-// Tests the current split's patterns in order, 64 per step.
+// Tests queued patterns up to 64 at a time in queue order while at least
+// `want` are queued (all of them when `final`): lane l takes the l-th untested
+// pattern, finds its split by the running sum of the queued counts and
+// unranks it; a ballot gives the first member.  `want` starts at 2 (a block
+// that decodes early is tested before much of the order is walked) and doubles
+// to 64 per step.
 template <int M>
-__device__ void run_split(Walk<M>& c)
+__device__ void flush(Walk<M>& c, bool final)
 {
     const int lane = lane_id();
-    uint64_t count = 1;
+    while (!c.found && c.pending > 0 && (final || c.pending >= c.want)) {
+        const uint32_t chunk = c.pending < (uint32_t)ORBG_WAVE ? c.pending : (uint32_t)ORBG_WAVE;
+        c.want = c.want < (uint32_t)ORBG_WAVE ? 2 * c.want : (uint32_t)ORBG_WAVE;
+        const bool act = (uint32_t)lane < chunk;
+        bool got = false;
+        int e = c.qhead;
+        uint32_t idx = 0, acc = 0;
+        for (int k = 0; k < c.live && acc < chunk; ++k) {
+            const int sl = (c.qhead + k) % ORBG_ML_QCAP;
+            const uint32_t rem = c.Q[sl].total - c.Q[sl].first;
+            if (!got && (uint32_t)lane < acc + rem) {
+                got = true;
+                e = sl;
+                idx = c.Q[sl].first + ((uint32_t)lane - acc);
+            }
+            acc += rem;
+        }
+        int64_t a[M];
+        uint32_t cn[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) count = sat_mul(count, c.cnt[i]);
-    const uint64_t left = (uint64_t)c.budget - c.qbase;        // > 0 while the walk runs
-    const uint64_t lim = count < left ? count : left;
-    for (uint64_t base = 0; base < lim; base += ORBG_WAVE) {
-        const uint64_t u = base + (uint64_t)lane;
-        const bool act = u < lim;
+        for (int i = 0; i < M; ++i) {
+            a[i] = act ? c.Q[e].a[i] : 0;
+            cn[i] = act ? c.Q[e].cnt[i] : 1u;
+        }
         uint64_t s = c.s0;
-        if (act) unrank_product(c, u, [&](int r) { s ^= c.h[r]; });
+        if (act) unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) { s ^= c.h[r]; });
         const uint64_t hits = ballot(act && s == 0);
         if (hits != 0) {
             const int wl = __builtin_ctzll(hits);
-            c.q = (uint32_t)(c.qbase + base + (uint64_t)wl + 1);
+            c.q = (uint32_t)(c.qbase + (uint64_t)wl + 1);
             c.found = true;
             c.stop = true;
             if (lane == wl) {
                 int nw = 0;
-                unrank_product(c, u, [&](int r) { c.win[nw++] = (uint8_t)r; });
+                unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) { c.win[nw++] = (uint8_t)r; });
                 c.win[ORBG_ML_WINCAP] = (uint8_t)nw;
             }
             wave_lds_sync();
             c.nwin = (int)uni32(c.win[ORBG_ML_WINCAP]);
             return;
         }
+        // the chunk's patterns are tested: drop whole splits, advance the last one
+        c.qbase += chunk;
+        c.pending -= chunk;
+        uint32_t left = chunk;
+        while (left > 0) {
+            const int sl = c.qhead;
+            const uint32_t rem = uni32(c.Q[sl].total - c.Q[sl].first);
+            if (rem <= left) {
+                left -= rem;
+                c.qhead = (c.qhead + 1) % ORBG_ML_QCAP;
+                --c.live;
+            } else {
+                if (lane == 0) c.Q[sl].first += left;
+                left = 0;
+            }
+        }
+        wave_lds_sync();
     }
-    c.qbase += count;
-    if (c.qbase >= (uint64_t)c.budget) c.stop = true;
+}
+
+// Queues the current split (its product cut at the budget) and tests whole
+// steps of 64 queued patterns; at the budget, tests the rest and stops.
+template <int M>
+__device__ void push_split(Walk<M>& c)
+{
+    uint64_t count = 1;
+#pragma unroll
+    for (int i = 0; i < M; ++i) count = sat_mul(count, c.cnt[i]);
+    const uint64_t room = (uint64_t)c.budget - c.qbase - c.pending;        // > 0 while the walk runs
+    const uint32_t tot = (uint32_t)(count < room ? count : room);
+    const int slot = (c.qhead + c.live) % ORBG_ML_QCAP;                     // live < 64 here
+    if (lane_id() == 0) {
+        QEntry& q = c.Q[slot];
+#pragma unroll
+        for (int i = 0; i < ORBG_ML_MSEG; ++i) {
+            q.a[i] = i < M ? c.a[i < M ? i : 0] : 0;
+            q.cnt[i] = i < M ? (uint32_t)(c.cnt[i < M ? i : 0] > 0xffffffffull ? 0xffffffffull : c.cnt[i < M ? i : 0])
+                             : 1u;
+        }
+        q.first = 0;
+        q.total = tot;
+    }
+    wave_lds_sync();
+    ++c.live;
+    c.pending += tot;
+    // the only call of flush (one inlined copy of the unranking per kernel)
+    const bool fin = c.qbase + c.pending >= (uint64_t)c.budget;
+    if (fin || c.pending >= c.want) flush<M>(c, fin);
+    if (fin) c.stop = true;
 }
 
 // Splits of `rest` over segments I..M-1 in the nested-loop order.  The last two
@@ -290,7 +371,7 @@ __device__ void walk_splits(Walk<M>& c, int64_t rest)
         if (n == 0) return;
         c.a[I] = rest;
         c.cnt[I] = n;
-        run_split<M>(c);
+        push_split<M>(c);
     } else if constexpr (I == M - 2) {
         const int lane = lane_id();
         for (int64_t base = 0; base <= rest && !c.stop;) {
@@ -302,7 +383,7 @@ __device__ void walk_splits(Walk<M>& c, int64_t rest)
                 c.cnt[I] = seg_count(c.tbl, c.seg[I], av);
                 c.a[I + 1] = rest - av;
                 c.cnt[I + 1] = seg_count(c.tbl, c.seg[I + 1], rest - av);
-                run_split<M>(c);
+                push_split<M>(c);
             }
             base = seg_next(c.seg[I], base + ORBG_WAVE);
         }
@@ -360,7 +441,10 @@ __device__ void walk(Walk<M>& c)
         walk_splits<0, M>(c, W);
         if (c.stop) return;
         const int64_t nxt = next_total<0, M>(c, W + 1, NONE);
-        if (nxt == NONE) return;            // every pattern tested: abandoned
+        // no pattern left: only possible once the query limit is reached (the
+        // limit is at most 2^n, and for n >= 17 the order holds more than 2^16
+        // patterns), so the queue has been tested by then
+        if (nxt == NONE) return;
         W = uni64(nxt);
     }
 }
@@ -381,6 +465,7 @@ struct MlLds {
     uint16_t pi[ORBG_ML_LMAX + 1];      // pi[r] = received index of rank r
     int anc[ORBG_ML_MSEG + 2];          // anchor ranks, ascending
     uint8_t win[ORBG_ML_WINCAP + 1];    // winner's ranks, then their count
+    QEntry Q[ORBG_ML_QCAP];             // splits waiting to be tested
 };
 
 struct Model {
@@ -497,7 +582,7 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
 }
 
 template <int M>
-__device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint64_t s0, uint32_t budget,
+__device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint64_t s0, uint32_t limit,
                             bool& found, uint32_t& q, int& nwin)
 {
     Walk<M> c;
@@ -509,7 +594,12 @@ __device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint
         c.seg[i].len = md.I[i + 1] - md.I[i];
     }
     c.qbase = 0;
-    c.budget = budget;
+    c.pending = 0;
+    c.want = 2;
+    c.qhead = 0;
+    c.live = 0;
+    c.Q = S.Q;
+    c.budget = limit;
     c.s0 = s0;
     c.tbl = tbl;
     c.h = S.h;
@@ -517,7 +607,7 @@ __device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint
     c.nwin = 0;
     c.stop = false;
     c.found = false;
-    c.q = budget;
+    c.q = limit;
     walk<M>(c);
     found = c.found;
     q = c.q;
@@ -574,15 +664,18 @@ __global__ void __launch_bounds__(ORBG_WAVE) mline_kernel(MlineArgs a)
             wave_lds_sync();
             const Model md = fit_model(S, n, a.mseg, a.jdiv);
             m_used = md.m;
+            // queries to make: the budget, at most all 2^n patterns (they hold
+            // a member, so the walk ends at a hit before running out)
+            const uint32_t limit = (n < 17 && a.budget > (1u << n)) ? (1u << n) : a.budget;
             if (s0 == 0) {
                 found = true;
                 q = 1;
             } else {
                 switch (md.m) {
-                case 1: decode_walk<1>(md, a.table, S, s0, a.budget, found, q, nwin); break;
-                case 2: decode_walk<2>(md, a.table, S, s0, a.budget, found, q, nwin); break;
-                case 3: decode_walk<3>(md, a.table, S, s0, a.budget, found, q, nwin); break;
-                default: decode_walk<4>(md, a.table, S, s0, a.budget, found, q, nwin); break;
+                case 1: decode_walk<1>(md, a.table, S, s0, limit, found, q, nwin); break;
+                case 2: decode_walk<2>(md, a.table, S, s0, limit, found, q, nwin); break;
+                case 3: decode_walk<3>(md, a.table, S, s0, limit, found, q, nwin); break;
+                default: decode_walk<4>(md, a.table, S, s0, limit, found, q, nwin); break;
                 }
             }
         } else {

@@ -9,6 +9,7 @@
 #define ORBG_ML_MSEG 4           // largest number of segments
 #define ORBG_ML_WINCAP 64        // flips of one pattern: at most 16 per segment
 #define ORBG_ML_BUDGET_MAX 65536 // largest query budget (2^16)
+#define ORBG_ML_QCAP 64          // queued splits: fewer than 64 untested patterns plus one
 
 namespace orbg {
 
