@@ -433,19 +433,61 @@ __device__ int64_t next_total(const Walk<M>& c, int64_t need, int64_t bound)
     }
 }
 
+// Two segments: one pass over the first segment's values a <= W both queues
+// the splits (a, W - a) and finds the next weight, the smallest of a + (the
+// second segment's next value at or above W + 1 - a) and of the first
+// segment's next value at or above W + 1 alone (next_total's two cases).
+__device__ int64_t walk_level2(Walk<2>& c, int64_t W)
+{
+    const int lane = lane_id();
+    const int64_t need = W + 1;
+    int64_t best = seg_next(c.seg[0], need);
+    for (int64_t base = 0; base <= W;) {
+        const int64_t a = base + lane;
+        const bool m0 = a <= W && seg_member(c.seg[0], a);
+        const bool ok = m0 && seg_member(c.seg[1], W - a);
+        int64_t cand = NONE;
+        if (m0) {
+            const int64_t r = seg_next(c.seg[1], need - a);
+            if (r != NONE) cand = a + r;
+        }
+        const int64_t mn = wave_min_i64(cand);
+        best = mn < best ? mn : best;
+        for (uint64_t bal = ballot(ok); bal != 0 && !c.stop; bal &= bal - 1) {
+            const int64_t av = base + (int64_t)__builtin_ctzll(bal);
+            c.a[0] = av;
+            c.cnt[0] = seg_count(c.tbl, c.seg[0], av);
+            c.a[1] = W - av;
+            c.cnt[1] = seg_count(c.tbl, c.seg[1], W - av);
+            push_split<2>(c);
+        }
+        if (c.stop) return NONE;
+        base = seg_next(c.seg[0], base + ORBG_WAVE);
+    }
+    return best;
+}
+
 template <int M>
 __device__ void walk(Walk<M>& c)
 {
+    // No pattern left (next weight NONE) is only possible once the query limit
+    // is reached (the limit is at most 2^n, and for n >= 17 the order holds more
+    // than 2^16 patterns), so the queue has been tested by then.
     int64_t W = 0;
-    for (;;) {
-        walk_splits<0, M>(c, W);
-        if (c.stop) return;
-        const int64_t nxt = next_total<0, M>(c, W + 1, NONE);
-        // no pattern left: only possible once the query limit is reached (the
-        // limit is at most 2^n, and for n >= 17 the order holds more than 2^16
-        // patterns), so the queue has been tested by then
-        if (nxt == NONE) return;
-        W = uni64(nxt);
+    if constexpr (M == 2) {
+        for (;;) {
+            const int64_t nxt = walk_level2(c, W);
+            if (c.stop || nxt == NONE) return;
+            W = uni64(nxt);
+        }
+    } else {
+        for (;;) {
+            walk_splits<0, M>(c, W);
+            if (c.stop) return;
+            const int64_t nxt = next_total<0, M>(c, W + 1, NONE);
+            if (nxt == NONE) return;
+            W = uni64(nxt);
+        }
     }
 }
 
