@@ -358,25 +358,33 @@ __device__ void push_split(Walk<M>& c)
     if (fin) c.stop = true;
 }
 
-// Splits of `rest` over segments I..M-1 in the nested-loop order.  The last two
-// segments are searched 64 candidate values of W_{M-1} at a time (lane l takes
-// base + l; a ballot keeps those both segments can take, taken in ascending
-// order), and a stretch without candidates is skipped to the next value
-// segment M-2 can take.
+// One pass over the splits of `rest` among segments I..M-1, in the nested-loop
+// order of the splitting algorithm, queueing each; returns the smallest total
+// weight of those segments above `rest` (NONE if none, or once the walk
+// stops), which is where the walk goes next.  With W_I = a <= rest that total
+// is a + (the same for segments I+1.. above rest - a); a value of segment I
+// above rest stands alone (the later segments add 0), the smallest being its
+// next value above rest.  The last two segments are scanned 64 candidates of
+// W_{M-1} at a time (lane l takes base + l; a ballot keeps the splits, taken
+// in ascending order), an empty stretch skipped to segment M-2's next value.
 template <int I, int M>
-__device__ void walk_splits(Walk<M>& c, int64_t rest)
+__device__ int64_t walk_level(Walk<M>& c, int64_t rest)
 {
-    if constexpr (I == M - 1) {
-        const uint64_t n = seg_count(c.tbl, c.seg[I], rest);
-        if (n == 0) return;
-        c.a[I] = rest;
-        c.cnt[I] = n;
-        push_split<M>(c);
-    } else if constexpr (I == M - 2) {
+    const int64_t need = rest + 1;
+    int64_t best = seg_next(c.seg[I], need);
+    if constexpr (I == M - 2) {
         const int lane = lane_id();
-        for (int64_t base = 0; base <= rest && !c.stop;) {
+        for (int64_t base = 0; base <= rest;) {
             const int64_t a = base + lane;
-            const bool ok = a <= rest && seg_member(c.seg[I], a) && seg_member(c.seg[I + 1], rest - a);
+            const bool m0 = a <= rest && seg_member(c.seg[I], a);
+            const bool ok = m0 && seg_member(c.seg[I + 1], rest - a);
+            int64_t cand = NONE;
+            if (m0) {
+                const int64_t r = seg_next(c.seg[I + 1], need - a);
+                if (r != NONE) cand = a + r;
+            }
+            const int64_t mn = wave_min_i64(cand);
+            best = mn < best ? mn : best;
             for (uint64_t bal = ballot(ok); bal != 0 && !c.stop; bal &= bal - 1) {
                 const int64_t av = base + (int64_t)__builtin_ctzll(bal);
                 c.a[I] = av;
@@ -385,109 +393,44 @@ __device__ void walk_splits(Walk<M>& c, int64_t rest)
                 c.cnt[I + 1] = seg_count(c.tbl, c.seg[I + 1], rest - av);
                 push_split<M>(c);
             }
+            if (c.stop) return NONE;
             base = seg_next(c.seg[I], base + ORBG_WAVE);
         }
     } else {
-        for (int64_t a = 0; a <= rest && !c.stop; a = seg_next(c.seg[I], a + 1)) {
+        for (int64_t a = 0; a <= rest; a = seg_next(c.seg[I], a + 1)) {
             c.a[I] = a;
             c.cnt[I] = seg_count(c.tbl, c.seg[I], a);
-            walk_splits<I + 1, M>(c, rest - a);
+            const int64_t r = walk_level<I + 1, M>(c, rest - a);
+            if (c.stop) return NONE;
+            if (r != NONE && a + r < best) best = a + r;
         }
-    }
-}
-
-// Smallest total weight >= need of segments I..M-1 that is below `bound`
-// (else `bound`).  For the last two segments: a value a of segment M-2 at or
-// above `need` stands alone (the last segment adds 0), the smallest such is
-// its next value; below `need` the lanes take 64 candidates a at a time, each
-// adding the last segment's next value at or above need - a.
-template <int I, int M>
-__device__ int64_t next_total(const Walk<M>& c, int64_t need, int64_t bound)
-{
-    if constexpr (I == M - 1) {
-        const int64_t v = seg_next(c.seg[I], need);
-        return v < bound ? v : bound;
-    } else if constexpr (I == M - 2) {
-        int64_t best = seg_next(c.seg[I], need);
-        best = best < bound ? best : bound;
-        const int lane = lane_id();
-        for (int64_t base = 0; base < need && base < best;) {
-            const int64_t a = base + lane;
-            int64_t cand = NONE;
-            if (a < need && a < best && seg_member(c.seg[I], a)) {
-                const int64_t r = seg_next(c.seg[I + 1], need - a);
-                if (r != NONE) cand = a + r;
-            }
-            const int64_t m = wave_min_i64(cand);
-            best = m < best ? m : best;
-            base = seg_next(c.seg[I], base + ORBG_WAVE);
-        }
-        return best;
-    } else {
-        int64_t best = bound;
-        for (int64_t a = 0; a < best; a = seg_next(c.seg[I], a + 1)) {
-            const int64_t r = next_total<I + 1, M>(c, need - a, best - a);
-            if (a + r < best) best = a + r;
-        }
-        return best;
-    }
-}
-
-// Two segments: one pass over the first segment's values a <= W both queues
-// the splits (a, W - a) and finds the next weight, the smallest of a + (the
-// second segment's next value at or above W + 1 - a) and of the first
-// segment's next value at or above W + 1 alone (next_total's two cases).
-__device__ int64_t walk_level2(Walk<2>& c, int64_t W)
-{
-    const int lane = lane_id();
-    const int64_t need = W + 1;
-    int64_t best = seg_next(c.seg[0], need);
-    for (int64_t base = 0; base <= W;) {
-        const int64_t a = base + lane;
-        const bool m0 = a <= W && seg_member(c.seg[0], a);
-        const bool ok = m0 && seg_member(c.seg[1], W - a);
-        int64_t cand = NONE;
-        if (m0) {
-            const int64_t r = seg_next(c.seg[1], need - a);
-            if (r != NONE) cand = a + r;
-        }
-        const int64_t mn = wave_min_i64(cand);
-        best = mn < best ? mn : best;
-        for (uint64_t bal = ballot(ok); bal != 0 && !c.stop; bal &= bal - 1) {
-            const int64_t av = base + (int64_t)__builtin_ctzll(bal);
-            c.a[0] = av;
-            c.cnt[0] = seg_count(c.tbl, c.seg[0], av);
-            c.a[1] = W - av;
-            c.cnt[1] = seg_count(c.tbl, c.seg[1], W - av);
-            push_split<2>(c);
-        }
-        if (c.stop) return NONE;
-        base = seg_next(c.seg[0], base + ORBG_WAVE);
     }
     return best;
 }
 
+// Reliability weights in increasing order, each one's splits queued and tested.
+// No weight left (NONE) is only possible once the query limit is reached (the
+// limit is at most 2^n, and for n >= 17 the order holds more than 2^16
+// patterns), so the queue has been tested by then.
 template <int M>
 __device__ void walk(Walk<M>& c)
 {
-    // No pattern left (next weight NONE) is only possible once the query limit
-    // is reached (the limit is at most 2^n, and for n >= 17 the order holds more
-    // than 2^16 patterns), so the queue has been tested by then.
     int64_t W = 0;
-    if constexpr (M == 2) {
-        for (;;) {
-            const int64_t nxt = walk_level2(c, W);
-            if (c.stop || nxt == NONE) return;
-            W = uni64(nxt);
+    for (;;) {
+        int64_t nxt;
+        if constexpr (M == 1) {
+            const uint64_t n = seg_count(c.tbl, c.seg[0], W);
+            if (n != 0) {
+                c.a[0] = W;
+                c.cnt[0] = n;
+                push_split<1>(c);
+            }
+            nxt = seg_next(c.seg[0], W + 1);
+        } else {
+            nxt = walk_level<0, M>(c, W);
         }
-    } else {
-        for (;;) {
-            walk_splits<0, M>(c, W);
-            if (c.stop) return;
-            const int64_t nxt = next_total<0, M>(c, W + 1, NONE);
-            if (nxt == NONE) return;
-            W = uni64(nxt);
-        }
+        if (c.stop || nxt == NONE) return;
+        W = uni64(nxt);
     }
 }
 
