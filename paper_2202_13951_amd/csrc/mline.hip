@@ -17,12 +17,15 @@
 //      the integer splitting algorithm, each W_i among the partial weights its
 //      segment can take (the collection step); inside one split the Cartesian
 //      product of the partial sets, segment 1 outermost, each partial set by
-//      partial Hamming weight, then Landslide (= lexicographic) order.  The
-//      patterns of one split are tested 64 at a time: lane l takes product
-//      element base + l and unranks it (mixed radix over the segments, then the
-//      Hamming weight, then a lexicographic subset of the segment's ranks with
-//      the given sum) with a table of subset counts; a ballot of syndrome == 0
-//      gives the first member in order;
+//      partial Hamming weight, then Landslide (= lexicographic) order.  One
+//      pass per weight finds its splits (the last two segments 64 candidates
+//      at a time) and the next weight; each split joins a queue in LDS, and the
+//      queued patterns are tested up to 64 at a time across splits and
+//      weights: lane l takes the l-th untested pattern, finds its split and
+//      unranks it (mixed radix over the segments, then the Hamming weight, then
+//      a lexicographic subset of the segment's ranks with the given sum) with a
+//      table of subset counts; a ballot of syndrome == 0 gives the first member
+//      in order;
 //   5. codeword, queries, abandon flag; optionally the block's segment count.
 //
 // Exactness limits (checked by the host): n <= 128, n - k <= 64, m <= 4,
