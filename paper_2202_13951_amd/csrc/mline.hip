@@ -142,6 +142,13 @@ __device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
     return false;
 }
 
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
 {
 #pragma unroll
@@ -378,22 +385,27 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
     if constexpr (I == M - 2) {
         const int lane = lane_id();
         for (int64_t base = 0; base <= rest;) {
+            // per lane: candidate W_I = a, the partial-set sizes of (a, rest - a)
+            // and the next total above rest through a
             const int64_t a = base + lane;
             const bool m0 = a <= rest && seg_member(c.seg[I], a);
-            const bool ok = m0 && seg_member(c.seg[I + 1], rest - a);
+            uint64_t n0 = 0, n1 = 0;
             int64_t cand = NONE;
             if (m0) {
+                n1 = seg_count(c.tbl, c.seg[I + 1], rest - a);
+                if (n1 != 0) n0 = seg_count(c.tbl, c.seg[I], a);
                 const int64_t r = seg_next(c.seg[I + 1], need - a);
                 if (r != NONE) cand = a + r;
             }
             const int64_t mn = wave_min_i64(cand);
             best = mn < best ? mn : best;
-            for (uint64_t bal = ballot(ok); bal != 0 && !c.stop; bal &= bal - 1) {
-                const int64_t av = base + (int64_t)__builtin_ctzll(bal);
+            for (uint64_t bal = ballot(n1 != 0); bal != 0 && !c.stop; bal &= bal - 1) {
+                const int l = __builtin_ctzll(bal);
+                const int64_t av = base + (int64_t)l;
                 c.a[I] = av;
-                c.cnt[I] = seg_count(c.tbl, c.seg[I], av);
+                c.cnt[I] = readlane_u64(n0, l);
                 c.a[I + 1] = rest - av;
-                c.cnt[I + 1] = seg_count(c.tbl, c.seg[I + 1], rest - av);
+                c.cnt[I + 1] = readlane_u64(n1, l);
                 push_split<M>(c);
             }
             if (c.stop) return NONE;
