@@ -276,6 +276,7 @@ template <int M>
 __device__ void flush(Walk<M>& c, bool final)
 {
     const int lane = lane_id();
+    wave_lds_sync();                          // queue entries written by lane 0
     while (!c.found && c.pending > 0 && (final || c.pending >= c.want)) {
         const uint32_t chunk = c.pending < (uint32_t)ORBG_WAVE ? c.pending : (uint32_t)ORBG_WAVE;
         c.want = c.want < (uint32_t)ORBG_WAVE ? 2 * c.want : (uint32_t)ORBG_WAVE;
@@ -359,7 +360,7 @@ __device__ void push_split(Walk<M>& c)
         q.first = 0;
         q.total = tot;
     }
-    wave_lds_sync();
+    // (the entry is read in flush, which starts with an LDS sync)
     ++c.live;
     c.pending += tot;
     // the only call of flush (one inlined copy of the unranking per kernel)
