@@ -1,7 +1,7 @@
 // Full (m-line) ORBGRAND decode kernel for gfx950 (Sec. IV).
 //
 // Per block, one wave:
-//   1. the LLR row (n <= 128: one or two elements per lane), hard decision and
+//   1. the LLR row (n <= 256: up to four elements per lane), hard decision and
 //      base syndrome s0 (Sec. III-A); s0 == 0 is query 1;
 //   2. the full reliability order: keys (IEEE bits of |LLR|) << 32 | index sorted
 //      ascending by a register bitonic network; h_r = column of rank r, pi_r its
@@ -28,12 +28,12 @@
 //      in order;
 //   5. codeword, queries, abandon flag; optionally the block's segment count.
 //
-// Exactness limits (checked by the host): n <= 128, n - k <= 64, m <= 4,
+// Exactness limits (checked by the host): n <= 256, n - k <= 64, m <= 4,
 // budget <= 2^16.  A pattern with 17 or more flips inside one segment comes
 // after all 2^17 - 1 patterns made of proper subsets of its flips (each weighs
 // less, or the same with fewer flips, since every rank but rank 1 weighs at
 // least 1), so no query within 2^16 has more than 16 flips in a segment and
-// partial logistic weights stay below 16 * 128; the count table covers exactly
+// partial logistic weights stay below 16 * 256; the count table covers exactly
 // that range, and the order restricted to it agrees with the full order on its
 // first 2^17 patterns.
 #include "orbg_device.h"
@@ -45,7 +45,7 @@ namespace orbg {
 namespace {
 
 constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..16
-constexpr int SL = ORBG_ML_SMAX;          // partial logistic weights 0..2047
+constexpr int SL = ORBG_ML_SMAX;          // partial logistic weights 0..4095
 constexpr int64_t NONE = INT64_MAX;
 
 __device__ __forceinline__ uint32_t uni32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -78,7 +78,7 @@ __device__ __forceinline__ int wcap(const Seg& g) { return g.len < WL ? g.len : 
 
 // Relative logistic weight of w >= 1 flips with partial weight x, or -1.  The
 // range test comes first, so the one division left has operands below 2^32
-// (relative weights <= 1928, slopes <= 2^20).
+// (relative weights <= 3976, slopes <= 2^20).
 __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
 {
     const int64_t r = x - (int64_t)w * g.J;
@@ -182,7 +182,7 @@ struct Walk {
     uint64_t s0;
     const uint32_t* tbl;
     const uint64_t* h;      // LDS: column of each rank
-    uint8_t* win;           // LDS: the winner's ranks
+    uint16_t* win;          // LDS: the winner's ranks
     QEntry* Q;              // LDS: queued splits
     int nwin;
     bool stop, found;
@@ -311,8 +311,8 @@ __device__ void flush(Walk<M>& c, bool final)
             c.stop = true;
             if (lane == wl) {
                 int nw = 0;
-                unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) { c.win[nw++] = (uint8_t)r; });
-                c.win[ORBG_ML_WINCAP] = (uint8_t)nw;
+                unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) { c.win[nw++] = (uint16_t)r; });
+                c.win[ORBG_ML_WINCAP] = (uint16_t)nw;
             }
             wave_lds_sync();
             c.nwin = (int)uni32(c.win[ORBG_ML_WINCAP]);
@@ -465,7 +465,7 @@ struct MlLds {
     float L[ORBG_ML_LMAX + 1];          // L[r] = |LLR| of rank r
     uint16_t pi[ORBG_ML_LMAX + 1];      // pi[r] = received index of rank r
     int anc[ORBG_ML_MSEG + 2];          // anchor ranks, ascending
-    uint8_t win[ORBG_ML_WINCAP + 1];    // winner's ranks, then their count
+    uint16_t win[ORBG_ML_WINCAP + 1];   // winner's ranks, then their count
     QEntry Q[ORBG_ML_QCAP];             // splits waiting to be tested
 };
 
@@ -485,7 +485,9 @@ __device__ __forceinline__ void model_basic(Model& md, int n)
     for (int i = 0; i < ORBG_ML_MSEG; ++i) { md.J[i] = 0; md.B[i] = 1; }
 }
 
-// Fit with at most mreq segments (L in LDS, ranks 1..n).  Wave-uniform result.
+// Fit with at most mreq segments (L in LDS, ranks 1..n; h = n/2 <= 32 NK).
+// Wave-uniform result.
+template <int NK>
 __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
 {
     const int lane = lane_id();
@@ -497,25 +499,29 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
     wave_lds_sync();
     int na = 2;
     for (int it = 1; it < mreq; ++it) {
-        // lane l: candidate rank j = l + 1 strictly between two adjacent anchors
-        const int j = lane + 1;
-        int a = 0, b = 0;
-        for (int p = 0; p + 1 < na; ++p) {
-            const int lo = S.anc[p], hi = S.anc[p + 1];
-            if (j > lo && j < hi) { a = lo; b = hi; }
-        }
-        bool ok = (b != 0) && j <= h;
-        float gap = 0.0f;
-        if (ok) {
+        // candidate ranks j = l + 1 (and l + 65 when h can pass 64) of lane l,
+        // each strictly between two adjacent anchors: largest gap, smallest
+        // rank on ties, as the max of (gap bits, 0xffff - j)
+        auto gap_key = [&](int j) -> uint64_t {
+            int a = 0, b = 0;
+            for (int p = 0; p + 1 < na; ++p) {
+                const int lo = S.anc[p], hi = S.anc[p + 1];
+                if (j > lo && j < hi) { a = lo; b = hi; }
+            }
+            if (b == 0 || j > h) return 0ull;
             const float La = S.L[a], Lb = S.L[b];
             const float s = __fdiv_rn(__fsub_rn(Lb, La), (float)(b - a));
             const float t = __fmul_rn((float)(j - a), s);
             const float line = __fadd_rn(La, t);
-            gap = fabsf(__fsub_rn(S.L[j], line));
-            ok = !__builtin_isnan(gap);
+            const float gap = fabsf(__fsub_rn(S.L[j], line));
+            if (__builtin_isnan(gap)) return 0ull;
+            return ((uint64_t)__float_as_uint(gap) << 32) | (uint64_t)(0xffff - j);
+        };
+        uint64_t key = gap_key(lane + 1);
+        if constexpr (NK > 2) {
+            const uint64_t k2 = gap_key(lane + 1 + ORBG_WAVE);
+            key = k2 > key ? k2 : key;
         }
-        // largest gap, smallest rank on ties: max of (gap bits, 255 - j)
-        uint64_t key = ok ? (((uint64_t)__float_as_uint(gap) << 32) | (uint64_t)(255 - j)) : 0ull;
 #pragma unroll
         for (int d = 1; d < ORBG_WAVE; d <<= 1) {
             const uint64_t o = __shfl_xor(key, d, ORBG_WAVE);
@@ -524,7 +530,7 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
         key = (uint64_t)uni64((int64_t)key);
         if (key == 0ull) break;                                  // no rank left between anchors
         if ((uint32_t)(key >> 32) == 0u) break;                  // largest gap is 0
-        const int bj = 255 - (int)(key & 0xffffffffull);
+        const int bj = 0xffff - (int)(key & 0xffffffffull);
         if (lane == 0) {
             int p = na;
             while (p > 0 && S.anc[p - 1] > bj) { S.anc[p] = S.anc[p - 1]; --p; }
@@ -663,7 +669,7 @@ __global__ void __launch_bounds__(ORBG_WAVE) mline_kernel(MlineArgs a)
                 }
             }
             wave_lds_sync();
-            const Model md = fit_model(S, n, a.mseg, a.jdiv);
+            const Model md = fit_model<NK>(S, n, a.mseg, a.jdiv);
             m_used = md.m;
             // queries to make: the budget, at most all 2^n patterns (they hold
             // a member, so the walk ends at a hit before running out)
@@ -745,7 +751,8 @@ hipError_t launch_mline(const MlineArgs& a, int grid, hipStream_t stream)
 {
     if (a.nblocks <= 0) return hipSuccess;
     if (a.n <= ORBG_WAVE) mline_kernel<1><<<grid, ORBG_WAVE, 0, stream>>>(a);
-    else mline_kernel<2><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    else if (a.n <= 2 * ORBG_WAVE) mline_kernel<2><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    else mline_kernel<4><<<grid, ORBG_WAVE, 0, stream>>>(a);
     return hipGetLastError();
 }
 

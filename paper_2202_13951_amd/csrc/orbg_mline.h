@@ -4,8 +4,8 @@
 #include <stdint.h>
 
 #define ORBG_ML_WMAX 16          // flips per segment the order reaches within the budget limit
-#define ORBG_ML_SMAX 2048        // partial logistic weights 0..2047 (16 flips of ranks <= 128)
-#define ORBG_ML_LMAX 128         // largest code length (and segment length)
+#define ORBG_ML_SMAX 4096        // partial logistic weights 0..4095 (16 flips of ranks <= 256)
+#define ORBG_ML_LMAX 256         // largest code length (and segment length)
 #define ORBG_ML_MSEG 4           // largest number of segments
 #define ORBG_ML_WINCAP 64        // flips of one pattern: at most 16 per segment
 #define ORBG_ML_BUDGET_MAX 65536 // largest query budget (2^16)
@@ -18,7 +18,7 @@ struct MlineArgs {
     int n;
     int m;                     // n - k
     const uint64_t* cols;      // n packed parity-check columns
-    const uint64_t* rows;      // m x nk packed rows (nk = 1 for n <= 64, else 2)
+    const uint64_t* rows;      // m x nk packed rows (nk = 1, 2, 4 for n <= 64, 128, 256)
     int64_t nblocks;
     uint32_t budget;
     int mseg;                  // largest number of segments of the fit

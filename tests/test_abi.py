@@ -103,7 +103,7 @@ def test_1line_export_argument_errors(n, budget, j0, count, msg):
 
 @pytest.mark.parametrize("n,k,budget,seg,jdiv,bufs,msg", [
     (0, 0, 10, 2, 0, True, "n = 0"),
-    (129, 120, 10, 2, 0, True, "n = 129"),
+    (257, 240, 10, 2, 0, True, "n = 257"),
     (100, 30, 10, 2, 0, True, "n - k = 70"),
     (32, 26, 10, 0, 0, True, "segments = 0"),
     (32, 26, 10, 5, 0, True, "segments = 5"),

@@ -66,6 +66,18 @@ def test_bch127_113(gpu_device, ebn0, segments):
     assert want[3].max() == segments
 
 
+@pytest.mark.parametrize("ebn0", [4.0, 5.0])
+@pytest.mark.parametrize("segments", [2, 3])
+def test_rlc256_240(gpu_device, ebn0, segments):
+    """Length 256 (four keys per lane, fits up to rank 128)."""
+    H, G = codes.code("rlc256_240")
+    llr, _ = channel.awgn_llr(G, 1000, ebn0, seed=int(ebn0 * 10) + 900)
+    want = _both(H, llr, 10 ** 4, segments, False, gpu_device, f"rlc256 {ebn0} dB")
+    assert want[3].max() == segments
+    # some fits place an anchor above rank 64 (the second candidate of a lane)
+    assert any(max(O.fit_mline(llr[b], segments)[0][1:-1], default=0) > 64 for b in range(1000))
+
+
 def test_one_segment_is_the_1line_decoder(gpu_device):
     """One segment: the m-line kernel and the 1-line kernel (precomputed schedules)
     give the same results, and both equal the 1-line oracle."""
@@ -84,9 +96,10 @@ def test_one_segment_is_the_1line_decoder(gpu_device):
     (4, 2, 16, 1.0, 3, False), (8, 3, 2 ** 8, 1.0, 2, False), (12, 5, 2 ** 12, 1.5, 3, True),
     (33, 20, 30000, 2.0, 4, False), (63, 50, 20000, 2.5, 3, False), (64, 40, 65536, 2.0, 2, True),
     (65, 52, 20000, 2.5, 4, False), (100, 36, 3000, 2.5, 3, False), (128, 80, 5000, 3.0, 4, True),
-    (128, 64, 2000, 3.0, 2, False)])
+    (128, 64, 2000, 3.0, 2, False), (129, 100, 3000, 3.0, 3, False), (200, 170, 3000, 3.5, 2, True),
+    (256, 192, 2000, 3.0, 4, False)])
 def test_ragged_lengths(gpu_device, n, k, budget, ebn0, segments, jdiv):
-    """Ragged lengths with one and two keys per lane, n - k up to 64, budgets up to 2^16."""
+    """Ragged lengths with one, two and four keys per lane, n - k up to 64, budgets up to 2^16."""
     H = codes.rlc_H(n, k, seed=n * 7 + k)
     G = codes.generator_matrix(H)
     llr, _ = channel.awgn_llr(G, 300, ebn0, seed=n + 5 * k)
@@ -151,9 +164,9 @@ def test_empty_batch(gpu_device):
     cw, q, ab, ms = binding.orbg_decode_mline(H, llr, 100, 3)
     torch.cuda.synchronize()
     assert cw.shape == (0, 32) and ms.shape == (0,)
-    H256, _ = codes.code("rlc256_240")
-    with pytest.raises(binding.OrbgError):                    # n above 128
-        binding.orbg_decode_mline(H256, torch.zeros((4, 256), dtype=torch.float32, device=gpu_device), 100, 2)
+    H300 = codes.rlc_H(300, 280, seed=3)
+    with pytest.raises(binding.OrbgError):                    # n above 256
+        binding.orbg_decode_mline(H300, torch.zeros((4, 300), dtype=torch.float32, device=gpu_device), 100, 2)
 
 
 def test_bch_full_size_sampled(gpu_device):
