@@ -57,6 +57,11 @@ WORKLOADS = {
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
                               "budget 2^16, full ORBGRAND with a 2-line fit (Sec. IV) against its J/beta variant, "
                               "1-line and basic ORBGRAND on the same blocks"),
+    "rlc256_mline": dict(code="rlc256_234", n=256, k=234, ebn0=[5.0, 5.5, 6.0, 6.5],
+                         blocks=10 ** 5, budget=65536, mline=True, segments=3,
+                         desc="RLC(256,234) H=[P|I22] (the length and redundancy of CA-Polar[256,234]), BPSK/AWGN "
+                              "Eb/N0 5..6.5 dB step 0.5, 1e5 blocks per point, budget 2^16, full ORBGRAND with a "
+                              "3-line fit (Sec. IV) against its J/beta variant and basic ORBGRAND on the same blocks"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
     "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),
@@ -794,8 +799,8 @@ def run_learned(args, wl, dev):
 def run_mline(args, wl, dev):
     """Full m-line ORBGRAND over all points in one call per step (timed), then per
     point: BLER, queries and the segment counts of the fit, the same with the J/beta
-    rounding, and the 1-line and basic decoders on the same blocks at the same
-    budget, each timed on its own."""
+    rounding, and the 1-line (where its schedules reach the budget) and basic
+    decoders on the same blocks at the same budget, each timed on its own."""
     import torch
     from paper_2202_13951_amd import binding
     H, llr, sent = single_inputs(wl, dev)
@@ -846,7 +851,11 @@ def run_mline(args, wl, dev):
             return {"bler": ne_ / B, "errors": ne_, "bler_ci95": list(wilson(ne_, B)),
                     "mean_queries": float(qq.mean()), "abandoned": int(oab.sum().item()), "blocks_per_s": B / t}, e_
         binding.orbg_decode_ex(H, llr[:B], budget, out=(ocw, oq, oab))             # builds the schedules
-        binding.orbg_decode_1line(H, llr[:B], budget, j0=False, out=(ocw, oq, oab))
+        one_line_err = None
+        try:
+            binding.orbg_decode_1line(H, llr[:B], budget, j0=False, out=(ocw, oq, oab))
+        except binding.OrbgError as ex:                   # budget beyond the 1-line schedules for this n
+            one_line_err = str(ex)
         torch.cuda.synchronize()
         for p, e in enumerate(wl["ebn0"]):
             sl = slice(p * B, (p + 1) * B)
@@ -867,8 +876,11 @@ def run_mline(args, wl, dev):
                   "blocks_per_s": B / t, "queries_per_s": float(q_np[sl].sum()) / t}
             pt["jbeta"], _ = other(lambda s_: binding.orbg_decode_mline(H, llr[s_], budget, segments, jdiv=True,
                                                                         segments_out=False, out=(ocw, oq, oab)), sl)
-            pt["one_line"], e1 = other(lambda s_: binding.orbg_decode_1line(H, llr[s_], budget, j0=False,
-                                                                            out=(ocw, oq, oab)), sl)
+            if one_line_err is None:
+                pt["one_line"], _ = other(lambda s_: binding.orbg_decode_1line(H, llr[s_], budget, j0=False,
+                                                                               out=(ocw, oq, oab)), sl)
+            else:
+                pt["one_line"] = {"unsupported": one_line_err}
             pt["basic"], eb = other(lambda s_: binding.orbg_decode_ex(H, llr[s_], budget, out=(ocw, oq, oab)), sl)
             pt["only_mline_correct_vs_basic"] = int((~err[sl] & eb).sum())
             pt["only_basic_correct"] = int((err[sl] & ~eb).sum())

@@ -114,6 +114,7 @@ def code(name: str):
         "rlc64_52": lambda: rlc_H(64, 52, seed=6452),
         "rlc128_116": lambda: rlc_H(128, 116, seed=128116),
         "rlc256_240": lambda: rlc_H(256, 240, seed=256240),
+        "rlc256_234": lambda: rlc_H(256, 234, seed=256234),
         "rlc128_105": lambda: rlc_H(128, 105, seed=128105),
     }
     H = table[name]()

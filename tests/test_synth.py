@@ -35,7 +35,7 @@ def test_bch127_113_structure():
 
 
 def test_generator_bases_span_kernel():
-    for name in ["rlc32_26", "bch127_113", "rlc64_52", "rlc128_116", "rlc256_240", "rlc128_105"]:
+    for name in ["rlc32_26", "bch127_113", "rlc64_52", "rlc128_116", "rlc256_240", "rlc256_234", "rlc128_105"]:
         H, G = codes.code(name)
         n = H.shape[1]
         assert G.shape == (n - H.shape[0], n)
