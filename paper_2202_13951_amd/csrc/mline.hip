@@ -413,12 +413,22 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
             base = seg_next(c.seg[I], base + ORBG_WAVE);
         }
     } else {
-        for (int64_t a = 0; a <= rest; a = seg_next(c.seg[I], a + 1)) {
-            c.a[I] = a;
-            c.cnt[I] = seg_count(c.tbl, c.seg[I], a);
-            const int64_t r = walk_level<I + 1, M>(c, rest - a);
-            if (c.stop) return NONE;
-            if (r != NONE && a + r < best) best = a + r;
+        // 64 candidate values of W_I per step: membership and partial-set size
+        // per lane, then the members in ascending order
+        const int lane = lane_id();
+        for (int64_t base = 0; base <= rest;) {
+            const int64_t a = base + lane;
+            const uint64_t n0 = a <= rest ? seg_count(c.tbl, c.seg[I], a) : 0;
+            for (uint64_t bal = ballot(n0 != 0); bal != 0; bal &= bal - 1) {
+                const int l = __builtin_ctzll(bal);
+                const int64_t av = base + (int64_t)l;
+                c.a[I] = av;
+                c.cnt[I] = readlane_u64(n0, l);
+                const int64_t r = walk_level<I + 1, M>(c, rest - av);
+                if (c.stop) return NONE;
+                if (r != NONE && av + r < best) best = av + r;
+            }
+            base = seg_next(c.seg[I], base + ORBG_WAVE);
         }
     }
     return best;
