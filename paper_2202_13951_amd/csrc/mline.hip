@@ -375,9 +375,10 @@ __device__ void push_split(Walk<M>& c)
 // stops), which is where the walk goes next.  With W_I = a <= rest that total
 // is a + (the same for segments I+1.. above rest - a); a value of segment I
 // above rest stands alone (the later segments add 0), the smallest being its
-// next value above rest.  The last two segments are scanned 64 candidates of
-// W_{M-1} at a time (lane l takes base + l; a ballot keeps the splits, taken
-// in ascending order), an empty stretch skipped to segment M-2's next value.
+// next value above rest.  Every level takes 64 candidate values of W_I at a
+// time (lane l takes base + l; a ballot keeps the values the segment can take
+// -- at the last two segments, the splits -- taken in ascending order), an
+// empty stretch skipped to segment I's next value.
 template <int I, int M>
 __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
 {
