@@ -160,25 +160,27 @@ def query_breakdown(q, ab, err, budget, sweep=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 
 
 
 # Sources the basic and 1-line decode kernels (light and heavy pass, schedules,
-# launch) are compiled from: their HBM counters stay valid while these are unchanged.
+# launch) are compiled from, and those of the m-line kernel: committed HBM
+# counters stay valid while these are unchanged.
 DECODE_SOURCES = ("decode.hip", "orbg_device.h", "orbg_internal.h", "orbg_kernels.h", "schedule.hip")
+MLINE_SOURCES = ("mline.hip", "orbg_mline.h", "orbg_device.h", "orbg_internal.h")
 
 
-def kernel_fingerprint() -> str:
-    """sha256 (first 16 hex digits) over the names and contents of the decode kernels' sources."""
+def kernel_fingerprint(sources=DECODE_SOURCES) -> str:
+    """sha256 (first 16 hex digits) over the names and contents of the given kernel sources."""
     import hashlib
     h = hashlib.sha256()
-    for name in DECODE_SOURCES:
+    for name in sources:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2202_13951_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(workload: str, prefix: str = "decode_kernel", sources=DECODE_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of
     this workload, or None if there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"decode_kernel_{WORKLOADS[workload]['code']}.md")
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{WORKLOADS[workload]['code']}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -187,7 +189,7 @@ def profiled_traffic(workload: str):
             if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_fingerprint"):
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
-    if vals.get("source_fingerprint") != kernel_fingerprint() or "traffic_bytes_per_launch" not in vals:
+    if vals.get("source_fingerprint") != kernel_fingerprint(sources) or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -913,11 +915,20 @@ def run_mline(args, wl, dev):
         "kernel_ms": float(np.mean(kern_ms)),
         "per_point": per_point,
         "roofline": {"bound": "alu", "achieved": ops / kavg / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS, "traffic": None,
+                     "unit": "Tops/s (int32)", "frac": ops / kavg / PEAK_INT32_OPS,
+                     # counters were taken for the workload's own line count
+                     "traffic": (profiled_traffic(args.workload, "mline_kernel", MLINE_SOURCES)
+                                 if segments == wl["segments"] else None),
                      "kernel": "mline_kernel (one decode call)", "ops_per_launch": ops,
                      "hbm": {"achieved_GBps": hbm_bytes / kavg / 1e9, "peak_GBps": PEAK_HBM / 1e9,
                              "frac": hbm_bytes / kavg / PEAK_HBM, "bytes_per_launch": hbm_bytes}},
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         result["cpu_baseline"] = cpu_baseline(H, lambda p, c: llr[p * B:p * B + c].cpu().numpy(), P, B, budget,
