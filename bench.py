@@ -53,9 +53,9 @@ WORKLOADS = {
                               "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. IV) against basic ORBGRAND "
                               "on the same blocks"),
     "bch127_mline": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
-                         blocks=10 ** 6, budget=65536, mline=True, segments=2,
+                         blocks=10 ** 6, budget=10 ** 5, mline=True, segments=2,
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
-                              "budget 2^16, full ORBGRAND with a 2-line fit (Sec. IV) against its J/beta variant, "
+                              "budget 1e5, full ORBGRAND with a 2-line fit (Sec. IV) against its J/beta variant, "
                               "1-line and basic ORBGRAND on the same blocks"),
     "rlc256_mline": dict(code="rlc256_234", n=256, k=234, ebn0=[5.0, 5.5, 6.0, 6.5],
                          blocks=10 ** 5, budget=65536, mline=True, segments=3,
@@ -872,7 +872,8 @@ def run_mline(args, wl, dev):
             pt = {"bler": ne / B, "errors": ne, "bler_ci95": list(wilson(ne, B)),
                   "mean_queries": float(q_np[sl].mean()), "abandoned": int(ab_np[sl].sum()),
                   "breakdown": query_breakdown(q_np[sl], ab_np[sl], err[sl], budget,
-                                               sweep=(10 ** 2, 10 ** 3, 10 ** 4, 65536)),
+                                               sweep=tuple(b for b in (10 ** 2, 10 ** 3, 10 ** 4, 10 ** 5)
+                                                           if b < budget) + (budget,)),
                   "segments_used": {str(int(v)): float(c / B) for v, c in zip(vals, cnts)},
                   "segments_call_identical": same,
                   "blocks_per_s": B / t, "queries_per_s": float(q_np[sl].sum()) / t}

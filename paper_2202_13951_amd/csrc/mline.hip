@@ -29,13 +29,17 @@
 //   5. codeword, queries, abandon flag; optionally the block's segment count.
 //
 // Exactness limits (checked by the host): n <= 256, n - k <= 64, m <= 4,
-// budget <= 2^16.  A pattern with 17 or more flips inside one segment comes
-// after all 2^17 - 1 patterns made of proper subsets of its flips (each weighs
+// budget <= 2^20.  A pattern with 21 or more flips inside one segment comes
+// after all 2^21 - 1 patterns made of proper subsets of its flips (each weighs
 // less, or the same with fewer flips, since every rank but rank 1 weighs at
-// least 1), so no query within 2^16 has more than 16 flips in a segment and
-// partial logistic weights stay below 16 * 256; the count table covers exactly
-// that range, and the order restricted to it agrees with the full order on its
-// first 2^17 patterns.
+// least 1), so no query within 2^20 has more than 20 flips in a segment.  Nor
+// does one reach a partial logistic weight of 4096 or more: that needs at least
+// 17 flips in a segment of 205 ranks or more, and the patterns that differ only
+// there by as many flips with a smaller sum (over 10^24, those within the first
+// 200 ranks alone) all weigh less.  The count table covers w <= 20 and partial
+// weights below 4096; the order restricted to them agrees with the full order
+// on its first 2^20 patterns, and every division below has operands under 2^32
+// (4095 times a slope of at most 2^20).
 #include "orbg_device.h"
 #include "orbg_internal.h"
 #include "orbg_mline.h"
@@ -44,7 +48,7 @@ namespace orbg {
 
 namespace {
 
-constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..16
+constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..20
 constexpr int SL = ORBG_ML_SMAX;          // partial logistic weights 0..4095
 constexpr int64_t NONE = INT64_MAX;
 
@@ -76,13 +80,20 @@ struct Seg {
 
 __device__ __forceinline__ int wcap(const Seg& g) { return g.len < WL ? g.len : WL; }
 
+// Largest relative logistic weight of w flips in the segment that the order
+// reaches (the segment's own bound, capped below 4096).
+__device__ __forceinline__ int64_t lw_top(int64_t w, int64_t len)
+{
+    const int64_t m = lw_max(w, len);
+    return m < SL - 1 ? m : SL - 1;
+}
+
 // Relative logistic weight of w >= 1 flips with partial weight x, or -1.  The
-// range test comes first, so the one division left has operands below 2^32
-// (relative weights <= 3976, slopes <= 2^20).
+// range test comes first, so the one division left has operands below 2^32.
 __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
 {
     const int64_t r = x - (int64_t)w * g.J;
-    if (r < lw_min(w) * g.B || r > lw_max(w, g.len) * g.B) return -1;
+    if (r < lw_min(w) * g.B || r > lw_top(w, g.len) * g.B) return -1;
     if (g.B == 1) return r;
     const uint32_t rr = (uint32_t)r, bb = (uint32_t)g.B, wp = rr / bb;
     return wp * bb == rr ? (int64_t)wp : -1;
@@ -93,7 +104,7 @@ __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
 // below stop at the first w whose smallest weight passes x.
 __device__ __forceinline__ int64_t min_weight(const Seg& g, int w) { return (int64_t)w * g.J + g.B * lw_min(w); }
 
-// Number of partial patterns (at most 16 flips) of the segment with partial
+// Number of partial patterns (at most 20 flips) of the segment with partial
 // weight x; the empty one has weight 0.
 __device__ uint64_t seg_count(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x)
 {
@@ -113,7 +124,7 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
     int64_t best = NONE;
     const int wc = wcap(g);
     for (int w = 1; w <= wc; ++w) {
-        const int64_t lo = lw_min(w), hi = lw_max(w, g.len), need = x - (int64_t)w * g.J;
+        const int64_t lo = lw_min(w), hi = lw_top(w, g.len), need = x - (int64_t)w * g.J;
         int64_t wp;
         if (need <= lo * g.B) {
             // the smallest weight of w flips is >= x; larger w only give more
@@ -123,7 +134,7 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
         } else if (need > hi * g.B) {
             continue;                                  // ceil(need / B) > hi
         } else {
-            const uint32_t nn = (uint32_t)need, bb = (uint32_t)g.B;
+            const uint32_t nn = (uint32_t)need, bb = (uint32_t)g.B;      // nn + bb - 1 < 2^32
             wp = g.B == 1 ? need : (int64_t)((nn + bb - 1u) / bb);
         }
         const int64_t c = (int64_t)w * g.J + g.B * wp;
@@ -132,7 +143,7 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
     return best;
 }
 
-// Can the segment take partial weight x (some partial Hamming weight <= 16)?
+// Can the segment take partial weight x (some partial Hamming weight <= 20)?
 __device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
 {
     if (x == 0) return true;
@@ -161,7 +172,7 @@ __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
 
 // A split waiting to be tested (LDS ring of ORBG_ML_QCAP entries): its partial
 // weights, partial-set sizes (saturated at 2^32 - 1, exact for product indices
-// below 2^16), the first product element not yet tested and the number of
+// below 2^20), the first product element not yet tested and the number of
 // elements to test (the product size, cut at the budget).
 struct QEntry {
     int64_t a[ORBG_ML_MSEG];
@@ -242,7 +253,7 @@ template <int M, typename F>
 __device__ __forceinline__ void unrank_product(const Seg (&seg)[M], const uint32_t* tbl, const int64_t (&a)[M],
                                                const uint32_t (&cnt)[M], uint32_t u, F&& emit)
 {
-    // u < 2^16: a radix above u leaves the digit u and quotient 0
+    // u < 2^20: a radix above u leaves the digit u and quotient 0
     uint32_t t[M];
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
@@ -437,7 +448,7 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
 
 // Reliability weights in increasing order, each one's splits queued and tested.
 // No weight left (NONE) is only possible once the query limit is reached (the
-// limit is at most 2^n, and for n >= 17 the order holds more than 2^16
+// limit is at most 2^n, and for n >= 21 the order holds more than 2^20
 // patterns), so the queue has been tested by then.
 template <int M>
 __device__ void walk(Walk<M>& c)
@@ -687,7 +698,7 @@ __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(
             m_used = md.m;
             // queries to make: the budget, at most all 2^n patterns (they hold
             // a member, so the walk ends at a hit before running out)
-            const uint32_t limit = (n < 17 && a.budget > (1u << n)) ? (1u << n) : a.budget;
+            const uint32_t limit = (n < 21 && a.budget > (1u << n)) ? (1u << n) : a.budget;
             if (s0 == 0) {
                 found = true;
                 q = 1;

@@ -3,12 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define ORBG_ML_WMAX 16          // flips per segment the order reaches within the budget limit
-#define ORBG_ML_SMAX 4096        // partial logistic weights 0..4095 (16 flips of ranks <= 256)
+#define ORBG_ML_WMAX 20          // flips per segment the order reaches within the budget limit
+#define ORBG_ML_SMAX 4096        // partial logistic weights 0..4095 (the order reaches no larger one)
 #define ORBG_ML_LMAX 256         // largest code length (and segment length)
 #define ORBG_ML_MSEG 4           // largest number of segments
-#define ORBG_ML_WINCAP 64        // flips of one pattern: at most 16 per segment
-#define ORBG_ML_BUDGET_MAX 65536 // largest query budget (2^16)
+#define ORBG_ML_WINCAP 80        // flips of one pattern: at most 20 per segment
+#define ORBG_ML_BUDGET_MAX 1048576  // largest query budget (2^20)
 #define ORBG_ML_QCAP 64          // queued splits: fewer than 64 untested patterns plus one
 
 namespace orbg {

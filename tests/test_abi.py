@@ -109,7 +109,7 @@ def test_1line_export_argument_errors(n, budget, j0, count, msg):
     (32, 26, 10, 5, 0, True, "segments = 5"),
     (32, 26, 10, 2, 2, True, "jdiv = 2"),
     (32, 26, 0, 2, 0, True, "budget = 0"),
-    (32, 26, 65537, 2, 0, True, "budget = 65537"),
+    (32, 26, (1 << 20) + 1, 2, 0, True, "budget = 1048577"),
     (32, 26, 100, 2, 0, False, "device buffer is NULL"),
 ])
 def test_mline_argument_errors(n, k, budget, seg, jdiv, bufs, msg):

@@ -99,7 +99,7 @@ def test_one_segment_is_the_1line_decoder(gpu_device):
     (128, 64, 2000, 3.0, 2, False), (129, 100, 3000, 3.0, 3, False), (200, 170, 3000, 3.5, 2, True),
     (256, 192, 2000, 3.0, 4, False)])
 def test_ragged_lengths(gpu_device, n, k, budget, ebn0, segments, jdiv):
-    """Ragged lengths with one, two and four keys per lane, n - k up to 64, budgets up to 2^16."""
+    """Ragged lengths with one, two and four keys per lane, n - k up to 64."""
     H = codes.rlc_H(n, k, seed=n * 7 + k)
     G = codes.generator_matrix(H)
     llr, _ = channel.awgn_llr(G, 300, ebn0, seed=n + 5 * k)
@@ -153,9 +153,10 @@ def test_budget_edges(gpu_device):
     H = codes.rlc_H(40, 20, seed=6)
     rng = np.random.default_rng(9)
     llr = rng.standard_normal((200, 40)).astype(np.float32)
-    for budget in (1, 2, 63, 64, 65, 127, 4097, 65536):
+    for budget in (1, 2, 63, 64, 65, 127, 4097, 65536, 1 << 18):
         want = _both(H, llr, budget, 3, False, gpu_device, "budget edges")
     assert want[2].sum() > 0
+    want = _both(H, llr[:40], 1 << 20, 2, False, gpu_device, "budget 2^20")
 
 
 def test_empty_batch(gpu_device):
