@@ -186,3 +186,37 @@ def test_bch_full_size_sampled(gpu_device):
     ok = np.nonzero(ab == 0)[0][:2000]
     syn = (cw[ok].astype(np.int64) @ H.T.astype(np.int64)) % 2
     assert not syn.any()
+
+
+def test_hip_graph_replay(gpu_device):
+    """The m-line decode captured in a graph (after the first call has built the
+    count table): every replay, with eager work in between, equals the eager
+    result, segment counts included."""
+    print("m-line graph replay", flush=True)
+    H, G = codes.code("bch127_113")
+    llr, _ = channel.awgn_llr(G, 4000, 4.5, seed=809)
+    x = torch.from_numpy(llr).to(gpu_device)
+    budget = 10 ** 4
+    eager = _gpu(H, llr, budget, 3, False, gpu_device)
+    N, n = llr.shape
+    s = torch.cuda.Stream()
+    cw = torch.zeros((N, n), dtype=torch.uint8, device=gpu_device)
+    q = torch.zeros(N, dtype=torch.int64, device=gpu_device)
+    ab = torch.zeros(N, dtype=torch.uint8, device=gpu_device)
+    ms = torch.zeros(N, dtype=torch.int32, device=gpu_device)
+    with torch.cuda.stream(s):                                  # warm-up on the capture stream
+        binding.orbg_decode_mline(H, x, budget, 3, segments_out=ms, out=(cw, q, ab), stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        binding.orbg_decode_mline(H, x, budget, 3, segments_out=ms, out=(cw, q, ab), stream=s)
+    for rep in range(3):
+        cw.fill_(7)
+        q.fill_(-1)
+        ab.fill_(9)
+        ms.fill_(-9)
+        _gpu(H, llr, budget, 2, True, gpu_device)               # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = (cw.cpu().numpy(), q.cpu().numpy().astype(np.uint64), ab.cpu().numpy(), ms.cpu().numpy())
+        _assert_same(got, eager, f"replay {rep}")
