@@ -68,10 +68,15 @@ def features(llr: np.ndarray) -> np.ndarray:
     return bf16_round(a * np.float32(FEATURE_SCALE))
 
 
-def forward(params: np.ndarray, x: np.ndarray, round_activations: bool = True):
-    """Returns (logits [N,64] fp64, cache).  x: [N,128] (BF16 values)."""
+def forward(params: np.ndarray, x: np.ndarray, round_activations: bool = True, round_weights: bool = True):
+    """Returns (logits [N,64] fp64, cache).  x: [N,128] (BF16 values).
+    round_weights / round_activations = False give the same network in exact
+    (fp64) arithmetic, the form in which finite differences of the loss apply."""
     p = unflatten(np.asarray(params, dtype=np.float64))
-    W = {k: bf16_round(p[k]).astype(np.float64) for k in ("W1", "W2", "W3")}
+    if round_weights:
+        W = {k: bf16_round(p[k]).astype(np.float64) for k in ("W1", "W2", "W3")}
+    else:
+        W = {k: p[k] for k in ("W1", "W2", "W3")}
     q = (lambda a: bf16_round(a).astype(np.float64)) if round_activations else (lambda a: a)
     x = np.asarray(x, dtype=np.float64)
     z1 = x @ W["W1"].T + p["b1"]
@@ -95,9 +100,10 @@ def loss_and_dlogits(logits: np.ndarray, labels: np.ndarray):
     return loss, d / N
 
 
-def backward(params: np.ndarray, x: np.ndarray, labels: np.ndarray, round_activations: bool = True):
+def backward(params: np.ndarray, x: np.ndarray, labels: np.ndarray, round_activations: bool = True,
+             round_weights: bool = True):
     """Returns (loss, flat gradient fp64)."""
-    logits, c = forward(params, x, round_activations)
+    logits, c = forward(params, x, round_activations, round_weights)
     loss, dl = loss_and_dlogits(logits, labels)
     W = c["W"]
     g = {}

@@ -135,3 +135,82 @@ def test_order_descending_ties_low_index():
     o = M.order(logits)[0]
     assert list(o[:2]) == [5, 9] and o[-1] == 1 and sorted(o) == list(range(64))
     assert list(o[2:8]) == [0, 2, 3, 4, 6, 7]
+
+
+def _offsets():
+    offs, o = {}, 0
+    for name, shape in M.SHAPES:
+        offs[name] = o
+        o += int(np.prod(shape))
+    return offs
+
+
+def test_weight_gradients_match_central_differences():
+    """Every weight matrix's gradient against fp64 central differences of the
+    loss, in the exact-arithmetic form of the network (weights and activations
+    not rounded), at entries of W1, W2 (an off-diagonal pair (i, j) / (j, i)
+    whose two gradients differ, so a transposed gradient fails) and W3."""
+    rng = np.random.default_rng(11)
+    d = M.unflatten(M.init(13).astype(np.float64) * 0.5)
+    for name in ("b1", "b2", "b3"):
+        d[name][:] = rng.standard_normal(d[name].shape) * 0.1
+    p = M.flatten(d)
+    x = M.bf16_round(rng.standard_normal((8, 128))).astype(np.float64)
+    labels = rng.integers(0, 64, 8)
+    _, g = M.backward(p, x, labels, round_activations=False, round_weights=False)
+    offs = _offsets()
+    entries = [("W1", (5, 17)), ("W1", (200, 127)), ("W1", (17, 5)),
+               ("W2", (3, 40)), ("W2", (40, 3)), ("W2", (255, 0)), ("W2", (128, 128)),
+               ("W3", (0, 255)), ("W3", (63, 7)), ("W3", (7, 63))]
+    eps = 1e-6
+    fd = {}
+    for name, (r, c) in entries:
+        cols = dict(M.SHAPES)[name][1]
+        i = offs[name] + r * cols + c
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        lp, _ = M.loss_and_dlogits(M.forward(pp, x, False, False)[0], labels)
+        lm, _ = M.loss_and_dlogits(M.forward(pm, x, False, False)[0], labels)
+        fd[(name, r, c)] = (lp - lm) / (2 * eps)
+        assert abs(fd[(name, r, c)] - g[i]) < 1e-8 + 1e-5 * abs(fd[(name, r, c)]), (name, r, c, fd[(name, r, c)], g[i])
+    # the pair (3, 40) / (40, 3) of W2 tells a transposed gradient apart
+    a, b = fd[("W2", 3, 40)], fd[("W2", 40, 3)]
+    assert abs(a - b) > 1e-3 * max(abs(a), abs(b)) and max(abs(a), abs(b)) > 1e-6
+    gw = M.unflatten(g)
+    assert abs(gw["W2"].T[3, 40] - a) > 1e-7 + 1e-5 * abs(a)
+
+
+def test_planted_gradient_mistakes_fail_the_difference_check():
+    """The central-difference check above rejects a transposed W2 gradient and a
+    W1 gradient formed with the hidden activations in place of the inputs: both
+    mistakes planted in a copy of the reference's backward."""
+    rng = np.random.default_rng(12)
+    d = M.unflatten(M.init(14).astype(np.float64) * 0.5)
+    p = M.flatten(d)
+    x = M.bf16_round(rng.standard_normal((6, 128))).astype(np.float64)
+    labels = rng.integers(0, 64, 6)
+    logits, c = M.forward(p, x, False, False)
+    _, dl = M.loss_and_dlogits(logits, labels)
+    W = c["W"]
+    dz2 = (dl @ W["W3"]) * (c["z2"] > 0)
+    dz1 = (dz2 @ W["W2"]) * (c["z1"] > 0)
+    wrong_W2 = (dz2.T @ c["h1"]).T
+    wrong_W1 = dz1.T @ c["h1"][:, :128]
+    offs = _offsets()
+    eps = 1e-6
+
+    def fd(name, r, cc):
+        i = offs[name] + r * dict(M.SHAPES)[name][1] + cc
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        lp, _ = M.loss_and_dlogits(M.forward(pp, x, False, False)[0], labels)
+        lm, _ = M.loss_and_dlogits(M.forward(pm, x, False, False)[0], labels)
+        return (lp - lm) / (2 * eps)
+
+    bad_w2 = [abs(fd("W2", r, cc) - wrong_W2[r, cc]) > 1e-8 + 1e-5 * abs(wrong_W2[r, cc])
+              for r, cc in ((3, 40), (40, 3), (100, 9))]
+    bad_w1 = [abs(fd("W1", r, cc) - wrong_W1[r, cc]) > 1e-8 + 1e-5 * abs(wrong_W1[r, cc])
+              for r, cc in ((5, 17), (17, 5), (200, 127))]
+    assert any(bad_w2) and any(bad_w1)
