@@ -160,3 +160,61 @@ def test_mixed_full_size_sampled(gpu_device):
         ok = ab[sel] == 0
         assert not syn[ok].any(), NAMES[ci]
         del allpos, words, syn
+
+
+STREAM_NAMES = ["rlc64_52", "bch127_113", "rlc128_116", "rlc256_240"]
+_STREAM_CACHE = {}
+
+
+def _stream_case(dev):
+    """The request stream's code set (four codes, one of odd length) in one flat
+    buffer, every block with its own Eb/N0 uniform in [3, 6] dB, budget 10^5."""
+    if "case" not in _STREAM_CACHE:
+        HG = [codes.code(nm) for nm in STREAM_NAMES]
+        N = 40000
+        llr, _, bc, ro, _ = mixed.mixed_llr_torch_snr_range([G for _, G in HG], [1, 1, 1, 1], N, 3.0, 6.0,
+                                                            seed=5150, device=dev)
+        _STREAM_CACHE["case"] = (HG, N, llr, bc, ro)
+    return _STREAM_CACHE["case"]
+
+
+@pytest.mark.parametrize("shape", ["stream", "mixed_tuned"])
+def test_stream_code_set_matches_oracle(gpu_device, shape):
+    """The request stream's four codes (RLC(64,52), BCH(127,113), RLC(128,116),
+    RLC(256,240)) shuffled into one mixed launch, in the stream's launch shape
+    (chunk 1, split after 16 steps, 16 heavy waves: the heavy pass on) and in the
+    tuned bulk shape.  Sampled blocks of every code, among them each code's
+    deepest searches, against the oracle element by element (codeword, queries,
+    abandon flag)."""
+    from paper_2202_13951_amd import autotune
+    print(f"stream code set, {shape} shape", flush=True)
+    HG, N, llr, bc, ro = _stream_case(gpu_device)
+    budget = 10 ** 5
+    if shape == "stream":
+        params = binding.LaunchParams(workgroups_per_cu=32, chunk=1, split_steps=16, heavy_waves=16,
+                                      heavy_workgroups_per_cu=2)
+    else:
+        params = binding.LaunchParams(**autotune.load_tuned("mixed"))
+    ids = [binding.orbg_code_register(H) for H, _ in HG]
+    cw = torch.zeros(llr.numel(), dtype=torch.uint8, device=gpu_device)
+    q = torch.zeros(N, dtype=torch.int64, device=gpu_device)
+    ab = torch.zeros(N, dtype=torch.uint8, device=gpu_device)
+    binding.orbg_decode_mixed(ids, bc, ro, llr, budget, cw, q, ab, params=params)
+    torch.cuda.synchronize()
+    qn, abn, bcn, ron = q.cpu().numpy().astype(np.uint64), ab.cpu().numpy(), bc.cpu().numpy(), ro.cpu().numpy()
+    cwn, llrn = cw.cpu().numpy(), llr.cpu().numpy()
+    assert ((qn >= 1) & (qn <= budget)).all()
+    if shape == "stream":
+        assert (qn > 16 * 64).sum() >= 20                # the heavy pass took part
+    rng = np.random.default_rng(17)
+    for ci, (H, G) in enumerate(HG):
+        n = H.shape[1]
+        mine = np.nonzero(bcn == ci)[0]
+        idx = np.unique(np.concatenate([rng.choice(mine, 300, replace=False), mine[np.argsort(qn[mine])[-12:]]]))
+        key = (ci, idx.tobytes())
+        if key not in _STREAM_CACHE:
+            _STREAM_CACHE[key] = O.decode(H, _rows(llrn, ron, n, idx), budget, THREADS)
+        ocw, oq, oab = _STREAM_CACHE[key]
+        assert (_rows(cwn, ron, n, idx) == ocw).all(), STREAM_NAMES[ci]
+        assert (qn[idx] == oq).all(), STREAM_NAMES[ci]
+        assert (abn[idx] == oab).all(), STREAM_NAMES[ci]
