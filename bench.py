@@ -15,7 +15,7 @@ heavy pass.
 --workload learned: the learned batch-order proposal on RLC(128,105), trained
 on the GPU, against plain ORBGRAND on the same held-out blocks.
 --workload bch127_1line: the default workload decoded by 1-line ORBGRAND (the
-one-segment fit of Sec. IV), with basic ORBGRAND on the same blocks per point.
+one-segment fit of Sec. III-E), with basic ORBGRAND on the same blocks per point.
 --workload stream: Poisson request arrivals (single blocks of four codes) served
 by a host loop of mixed-code launches; p50/p99 latency and blocks/s at 1e5 and
 1e6 requests/s.
@@ -50,18 +50,18 @@ WORKLOADS = {
     "bch127_1line": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
                          blocks=10 ** 6, budget=10 ** 5, oneline=True,
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
-                              "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. IV) against basic ORBGRAND "
+                              "budget 1e5, 1-line ORBGRAND (one-segment fit, Sec. III-E) against basic ORBGRAND "
                               "on the same blocks"),
     "bch127_mline": dict(code="bch127_113", n=127, k=113, ebn0=[4.0, 4.5, 5.0, 5.5, 6.0, 6.5, 7.0],
                          blocks=10 ** 6, budget=10 ** 5, mline=True, segments=2,
                          desc="BCH(127,113) t=2, BPSK/AWGN Eb/N0 4..7 dB step 0.5, 1e6 blocks per point, "
-                              "budget 1e5, full ORBGRAND with a 2-line fit (Sec. IV) against its J/beta variant, "
+                              "budget 1e5, full ORBGRAND with a 2-line fit (Sec. III-D, III-E) against its J/beta variant, "
                               "1-line and basic ORBGRAND on the same blocks"),
     "rlc256_mline": dict(code="rlc256_234", n=256, k=234, ebn0=[5.0, 5.5, 6.0, 6.5],
                          blocks=10 ** 5, budget=65536, mline=True, segments=3,
                          desc="RLC(256,234) H=[P|I22] (the length and redundancy of CA-Polar[256,234]), BPSK/AWGN "
                               "Eb/N0 5..6.5 dB step 0.5, 1e5 blocks per point, budget 2^16, full ORBGRAND with a "
-                              "3-line fit (Sec. IV) against its J/beta variant and basic ORBGRAND on the same blocks"),
+                              "3-line fit (Sec. III-D, III-E) against its J/beta variant and basic ORBGRAND on the same blocks"),
     "rlc32": dict(code="rlc32_26", n=32, k=26, ebn0=[4.0], blocks=10 ** 4, budget=10 ** 4,
                   desc="RLC(32,26) H=[P|I6], BPSK/AWGN Eb/N0 4 dB, 1e4 blocks, budget 1e4, plain ORBGRAND"),
     "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),

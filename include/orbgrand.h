@@ -114,10 +114,10 @@ int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t bu
 
 /*
  * 1-line ORBGRAND decode (the one-segment case of the full ORBGRAND model of
- * Sec. IV, noted there as giving a small gain over the basic order).
+ * Sec. III-D, noted in Sec. IV-A as giving a small gain over the basic order).
  *
  * Each block's reliability curve is fitted with one line through its anchors at
- * ranks 1 and h = floor(n / 2) (Sec. IV, anchor-point fitting): slope
+ * ranks 1 and h = floor(n / 2) (Sec. III-E, anchor-point fitting): slope
  * Q = (L_h - L_1) / (h - 1), with L_j the |LLR| of rank j; quantised offset
  * J0 = [L_1 / Q] - 1, [x] = floor(x + 1/2) (eqs. (Q) and (quant) with m = 1,
  * beta = 1); each operation is FP32 rounded to nearest in that order.  A slope
@@ -147,7 +147,7 @@ int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t
                       int32_t* j0, const orbg_launch_params* params, void* stream);
 
 /*
- * Full (m-line) ORBGRAND decode (Sec. IV): per block, a piecewise-linear fit of
+ * Full (m-line) ORBGRAND decode (Sec. III-D; fit of Sec. III-E): per block, a piecewise-linear fit of
  * the sorted reliabilities with at most `segments` lines (anchor points from
  * ranks 1 and floor(n/2), each added anchor at the rank with the largest
  * vertical gap to the chord of its neighbouring anchors, smallest rank on
@@ -188,18 +188,23 @@ int orbg_code_release(int code_id);
  * ORBGRAND as in orbg_decode, for every block with its own code).
  * codes: HOST array of `ncodes` registered ids (1 <= ncodes <= 8, every code
  * with n <= 256, the n of all codes summing to at most 2048).
- * block_code: DEVICE u8 per block, an index into `codes`.
+ * block_code: DEVICE u8 per block, an index into `codes`; an index >= ncodes
+ * decodes the block with codes[0].
  * row_offset: DEVICE i64 per block, the offset (in elements) of the block's row
- * both in `llr` (FP32) and in `codeword` (bytes); rows hold the block's own n
- * values.  queries/abandoned: DEVICE, one entry per block.  Offsets and code
- * indices are not checked on the device: they must lie inside the buffers.
+ * both in `llr` (FP32, llr_len elements) and in `codeword` (bytes,
+ * codeword_len elements); rows hold the block's own n values.  A row that does
+ * not lie inside both buffers (offset < 0 or offset + n above either length)
+ * is read as zeros and its codeword stores are dropped; its queries and flag
+ * are still written.  queries/abandoned: DEVICE, one entry per block.
  * Blocks that need many queries move to the heavy pass and are searched by
  * several waves; the result is the same as orbg_decode's for each block.
+ * Errors: ORBG_EINVAL for a negative length, and as orbg_decode otherwise.
  */
 int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code,
-                      const int64_t* row_offset, const float* llr, int64_t batch,
-                      uint64_t budget, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
-                      const orbg_launch_params* params, void* stream);
+                      const int64_t* row_offset, const float* llr, int64_t llr_len, int64_t batch,
+                      uint64_t budget, uint8_t* codeword, int64_t codeword_len, uint64_t* queries,
+                      uint8_t* abandoned, const orbg_launch_params* params, void* stream);
+
 
 /*
  * Copies the first `count` entries of the library's basic-ORBGRAND query

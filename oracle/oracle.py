@@ -176,7 +176,7 @@ def permutation(llr: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# 1-line ORBGRAND (Sec. IV with one segment; readings R10, R11 in the C source)
+# 1-line ORBGRAND (Sec. III-D/III-E with one segment; readings R10, R11 in the C source)
 # ---------------------------------------------------------------------------
 NO_FORCE = -(1 << 63)
 
@@ -227,7 +227,7 @@ def decode_1line(H: np.ndarray, llr: np.ndarray, budget: int, threads: int = 1, 
 
 
 # ---------------------------------------------------------------------------
-# Full (m-line) ORBGRAND (Sec. IV; readings R12-R15 in the C source)
+# Full (m-line) ORBGRAND (Sec. III-D, fit of Sec. III-E; readings R12-R15 in the C source)
 # ---------------------------------------------------------------------------
 MMAX = 8
 

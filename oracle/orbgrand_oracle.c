@@ -41,12 +41,12 @@
  * batch), then the plain order continues from g = 4096.  The budget and the
  * abandonment rule are unchanged.
  *
- * 1-line ORBGRAND (the full ORBGRAND of Sec. IV with m = 1 segment): the
+ * 1-line ORBGRAND (the full ORBGRAND of Sec. III-D with m = 1 segment): the
  * reliability of rank j is modelled as J0 + beta j (eq. (relest_seg)), so a
  * pattern's reliability weight is J0 w + beta W (eq. (W2IJ)) with w its Hamming
  * and W its logistic weight; patterns are taken by increasing reliability
  * weight, and inside one weight by the rules above.  Fitting and quantization
- * (Sec. IV, eqs. (Q), (quant)) with m = 1:
+ * (Sec. III-E, eqs. (Q), (quant)) with m = 1:
  *   R10 the anchor points are ranks 1 and h = floor(n/2) and the one line joins
  *       them (the central line extended over the whole curve), so
  *       Q = (L_h - L_1) / (h - 1), beta = [Q / Q] = 1 and J0 = [L_1 / Q] - 1,
@@ -56,7 +56,7 @@
  *       ORBGRAND), and J0 is capped at 2^20 (far beyond any weight reached).
  *   With J0 = 0 the order is the basic one.
  *
- * Full ORBGRAND (Sec. IV with m segments, the fit of eqs. (Q), (quant) and the
+ * Full ORBGRAND (Sec. III-D with m segments, the fit of eqs. (Q), (quant) and the
  * J/beta variant) follows at the end of the file with readings R12-R15.
  *
  * Parity status: every function here is pinned by tests (brute-force
@@ -619,7 +619,7 @@ void oracle_permutation(const float* llr, int n, int* pi)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Full (m-line) ORBGRAND, Sec. IV.                                           */
+/* Full (m-line) ORBGRAND, Sec. III-D.                                          */
 /*                                                                            */
 /* Model (eq. (relest_seg)): segment i (1 <= i <= m) holds ranks              */
 /* I[i-1]+1 .. I[i], I[0] = 0, I[m] = n, and models the reliability of rank j */
@@ -628,7 +628,7 @@ void oracle_permutation(const float* llr, int n, int* pi)
 /* the Hamming weight and the logistic weight of its ranks in segment i,      */
 /* counted from the segment's start.                                          */
 /*                                                                            */
-/* Order (eq. (cartP) and the flow of Sec. IV): reliability weights W          */
+/* Order (eq. (cartP) and the flow of Sec. III-D): reliability weights W          */
 /* ascending; inside one W, the splitting patterns (W_1, ..., W_m),           */
 /* sum W, in the nested-loop order of the integer splitting algorithm (W_1    */
 /* ascending, then W_2, ...), only those whose every W_i has a valid partial  */
@@ -1005,7 +1005,7 @@ static int model_from(int n, int m, const int* I, const long* J, const long* bet
     return 0;
 }
 
-/* J/beta variant (complexity control of Sec. IV): each J_{i-1} replaced by
+/* J/beta variant (complexity control of Sec. III-D, rounding of Sec. III-E): each J_{i-1} replaced by
  * [J_{i-1} / beta_i] beta_i, with [x] = floor(x + 1/2) taken exactly. */
 static void model_jdiv(orbm_model_t* M)
 {

@@ -57,7 +57,7 @@ def load():
     L.orbg_code_register.restype = ci
     L.orbg_code_release.argtypes = [ci]
     L.orbg_code_release.restype = ci
-    L.orbg_decode_mixed.argtypes = [vp, ci, vp, vp, vp, i64, u64, vp, vp, vp, vp, vp]
+    L.orbg_decode_mixed.argtypes = [vp, ci, vp, vp, vp, i64, i64, u64, vp, i64, vp, vp, vp, vp]
     L.orbg_decode_mixed.restype = ci
     L.orbg_mlp_workspace_bytes.argtypes = [i64]
     L.orbg_mlp_workspace_bytes.restype = i64
@@ -109,9 +109,52 @@ def _host_H(H) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(H), dtype=np.uint8)
 
 
+def _need(cond: bool, msg: str):
+    """Argument check that survives python -O (raises ValueError)."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _tensor_spec(t, name: str, dtype, shape=None, ndim=None):
+    """t must be a contiguous torch tensor of this dtype (and shape / rank)."""
+    import torch
+    _need(isinstance(t, torch.Tensor), f"{name} must be a torch tensor")
+    _need(t.dtype == dtype, f"{name} must be {dtype} (got {t.dtype})")
+    if ndim is not None:
+        _need(t.dim() == ndim, f"{name} must have {ndim} dimension(s)")
+    if shape is not None:
+        _need(tuple(t.shape) == tuple(shape), f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    _need(t.is_contiguous(), f"{name} must be contiguous")
+
+
+def _on_device(t, name: str, device=None):
+    _need(t.is_cuda, f"{name} must be on a CUDA device")
+    if device is not None:
+        _need(t.device == device, f"{name} is on {t.device}, expected {device}")
+
+
+def _dev_tensor(t, name: str, dtype, shape=None, device=None, ndim=None):
+    """t must be a contiguous CUDA tensor of this dtype (and shape / device / rank)."""
+    _tensor_spec(t, name, dtype, shape, ndim)
+    _on_device(t, name, device)
+
+
+def _llr_rows(llr, n: int):
+    """llr must be a CUDA float32 [N, n] tensor; returns N."""
+    import torch
+    _need(isinstance(llr, torch.Tensor) and llr.dim() == 2, "llr must be a 2-D torch tensor")
+    _dev_tensor(llr, "llr", torch.float32, shape=(llr.shape[0], n))
+    return llr.shape[0]
+
+
 def _outputs(N, n, device, out):
     import torch
     if out is not None:
+        _need(len(out) == 3, "out must be (codeword, queries, abandoned)")
+        cw, q, ab = out
+        _dev_tensor(cw, "codeword", torch.uint8, (N, n), device)
+        _dev_tensor(q, "queries", torch.int64, (N,), device)
+        _dev_tensor(ab, "abandoned", torch.uint8, (N,), device)
         return out
     return (torch.empty((N, n), dtype=torch.uint8, device=device),
             torch.empty((N,), dtype=torch.int64, device=device),
@@ -124,9 +167,7 @@ def orbg_decode(H, llr, budget: int, out=None, stream=None):
     on the same device (queries holds the u64 counts)."""
     Hn = _host_H(H)
     m, n = Hn.shape
-    assert llr.is_cuda and llr.dtype.__str__() == "torch.float32" and llr.is_contiguous()
-    assert llr.dim() == 2 and llr.shape[1] == n
-    N = llr.shape[0]
+    N = _llr_rows(llr, n)
     cw, q, ab = _outputs(N, n, llr.device, out)
     rc = load().orbg_decode(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
                             int(budget), N, ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
@@ -137,11 +178,11 @@ def orbg_decode(H, llr, budget: int, out=None, stream=None):
 
 def orbg_decode_ordered(H, llr, budget: int, order, out=None, stream=None):
     """Decode with a per-block order of the first 64 batches; order: CUDA uint8 [N, 64]."""
+    import torch
     Hn = _host_H(H)
     m, n = Hn.shape
-    assert llr.is_cuda and llr.is_contiguous() and llr.dim() == 2 and llr.shape[1] == n
-    N = llr.shape[0]
-    assert order.is_cuda and order.is_contiguous() and tuple(order.shape) == (N, 64)
+    N = _llr_rows(llr, n)
+    _dev_tensor(order, "order", torch.uint8, (N, 64), llr.device)
     cw, q, ab = _outputs(N, n, llr.device, out)
     rc = load().orbg_decode_ordered(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n,
                                     n - m, int(budget), N, ctypes.c_void_p(order.data_ptr()),
@@ -157,12 +198,12 @@ def _params_ptr(params):
 
 def orbg_decode_ex(H, llr, budget: int, order=None, params: LaunchParams | None = None, out=None, stream=None):
     """orbg_decode (order None) or orbg_decode_ordered with an explicit launch shape."""
+    import torch
     Hn = _host_H(H)
     m, n = Hn.shape
-    assert llr.is_cuda and llr.is_contiguous() and llr.dim() == 2 and llr.shape[1] == n
-    N = llr.shape[0]
+    N = _llr_rows(llr, n)
     if order is not None:
-        assert order.is_cuda and order.is_contiguous() and tuple(order.shape) == (N, 64)
+        _dev_tensor(order, "order", torch.uint8, (N, 64), llr.device)
     cw, q, ab = _outputs(N, n, llr.device, out)
     rc = load().orbg_decode_ex(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
                                int(budget), N, ctypes.c_void_p(order.data_ptr()) if order is not None else None,
@@ -178,16 +219,14 @@ def orbg_decode_1line(H, llr, budget: int, j0=True, params: LaunchParams | None 
     import torch
     Hn = _host_H(H)
     m, n = Hn.shape
-    assert llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()
-    assert llr.dim() == 2 and llr.shape[1] == n
-    N = llr.shape[0]
+    N = _llr_rows(llr, n)
     cw, q, ab = _outputs(N, n, llr.device, out)
     if j0 is True:
         j0 = torch.empty((N,), dtype=torch.int32, device=llr.device)
     elif j0 is False:
         j0 = None
     if j0 is not None:
-        assert j0.is_cuda and j0.dtype == torch.int32 and j0.is_contiguous() and j0.shape[0] == N
+        _dev_tensor(j0, "j0", torch.int32, (N,), llr.device)
     rc = load().orbg_decode_1line(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
                                   int(budget), N, ctypes.c_void_p(cw.data_ptr()), ctypes.c_void_p(q.data_ptr()),
                                   ctypes.c_void_p(ab.data_ptr()), _p(j0), _params_ptr(params),
@@ -203,17 +242,14 @@ def orbg_decode_mline(H, llr, budget: int, segments: int, jdiv: bool = False, se
     import torch
     Hn = _host_H(H)
     m, n = Hn.shape
-    assert llr.is_cuda and llr.dtype == torch.float32 and llr.is_contiguous()
-    assert llr.dim() == 2 and llr.shape[1] == n
-    N = llr.shape[0]
+    N = _llr_rows(llr, n)
     cw, q, ab = _outputs(N, n, llr.device, out)
     if segments_out is True:
         segments_out = torch.empty((N,), dtype=torch.int32, device=llr.device)
     elif segments_out is False:
         segments_out = None
     if segments_out is not None:
-        assert (segments_out.is_cuda and segments_out.dtype == torch.int32 and segments_out.is_contiguous()
-                and segments_out.shape[0] == N)
+        _dev_tensor(segments_out, "segments_out", torch.int32, (N,), llr.device)
     rc = load().orbg_decode_mline(Hn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(llr.data_ptr()), n, n - m,
                                   int(budget), N, int(segments), int(bool(jdiv)), ctypes.c_void_p(cw.data_ptr()),
                                   ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(ab.data_ptr()), _p(segments_out),
@@ -240,17 +276,27 @@ def orbg_decode_mixed(code_ids, block_code, row_offset, llr, budget: int, codewo
                       params: LaunchParams | None = None, stream=None):
     """Mixed-code decode.  code_ids: registered ids; block_code: CUDA uint8 [N] index into
     code_ids; row_offset: CUDA int64 [N] element offset of each row in llr (float32, 1-D) and
-    codeword (uint8, 1-D); queries: CUDA int64 [N]; abandoned: CUDA uint8 [N]."""
+    codeword (uint8, 1-D); queries: CUDA int64 [N]; abandoned: CUDA uint8 [N].  The library
+    bounds every row by the lengths of llr and codeword (a row outside them reads zeros and
+    its codeword stores are dropped)."""
+    import torch
     ids = (ctypes.c_int * len(code_ids))(*[int(c) for c in code_ids])
+    _tensor_spec(block_code, "block_code", torch.uint8, ndim=1)
     N = block_code.shape[0]
-    for t in (block_code, row_offset, llr, codeword, queries, abandoned):
-        assert t.is_cuda and t.is_contiguous()
-    assert row_offset.shape[0] == N and queries.shape[0] == N and abandoned.shape[0] == N
+    spec = [(row_offset, "row_offset", torch.int64, (N,), None), (llr, "llr", torch.float32, None, 1),
+            (codeword, "codeword", torch.uint8, None, 1), (queries, "queries", torch.int64, (N,), None),
+            (abandoned, "abandoned", torch.uint8, (N,), None)]
+    for t, name, dt, shape, nd in spec:
+        _tensor_spec(t, name, dt, shape, nd)
+    dev = block_code.device
+    _on_device(block_code, "block_code")
+    for t, name, *_ in spec:
+        _on_device(t, name, dev)
     rc = load().orbg_decode_mixed(ids, len(code_ids), ctypes.c_void_p(block_code.data_ptr()),
-                                  ctypes.c_void_p(row_offset.data_ptr()), ctypes.c_void_p(llr.data_ptr()), N,
-                                  int(budget), ctypes.c_void_p(codeword.data_ptr()),
-                                  ctypes.c_void_p(queries.data_ptr()), ctypes.c_void_p(abandoned.data_ptr()),
-                                  _params_ptr(params), _stream_ptr(stream))
+                                  ctypes.c_void_p(row_offset.data_ptr()), ctypes.c_void_p(llr.data_ptr()),
+                                  llr.numel(), N, int(budget), ctypes.c_void_p(codeword.data_ptr()),
+                                  codeword.numel(), ctypes.c_void_p(queries.data_ptr()),
+                                  ctypes.c_void_p(abandoned.data_ptr()), _params_ptr(params), _stream_ptr(stream))
     _check("orbg_decode_mixed", rc)
 
 

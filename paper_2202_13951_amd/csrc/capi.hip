@@ -141,8 +141,9 @@ uint64_t round_up_pow2(uint64_t x)
     return p;
 }
 
-// Schedule with at least `need` entries for length n (need <= 2^n).
-int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule** out)
+// Schedule with at least `need` entries for length n (need <= 2^n).  build =
+// false only looks it up (ORBG_EINVAL if it has not been built yet).
+int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule** out, bool build = true)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
@@ -152,6 +153,9 @@ int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule*
     auto key = std::make_tuple(dev, n, len);
     auto it = g_sched.find(key);
     if (it != g_sched.end()) { *out = it->second; return ORBG_OK; }
+    if (!build)
+        return fail(ORBG_EINVAL, "no query schedule for n = %d and this budget on device %d yet (a call of "
+                    "orbg_decode_mixed with the same codes and budget builds it)", n, dev);
     orbg::Schedule* s = new orbg::Schedule;
     char err[256] = {0};
     const int rc = orbg_build_schedule(n, len, stream, s, err, sizeof(err));
@@ -264,12 +268,14 @@ int keys_per_lane(int n)
     return nk;
 }
 
-// Fills one code descriptor (schedule for `need` queries).
-int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_base, orbg::CodeDesc* d)
+// Fills one code descriptor (schedule for `need` queries; build = false: the
+// schedule must exist already).
+int describe(const CodeEntry* c, uint64_t need, hipStream_t st, uint32_t col_base, orbg::CodeDesc* d,
+             bool build = true)
 {
     if (c->n < 63 && need > (1ull << c->n)) need = 1ull << c->n;
     const orbg::Schedule* s = nullptr;
-    int rc = get_schedule(c->n, need, st, &s);
+    int rc = get_schedule(c->n, need, st, &s, build);
     if (rc) return rc;
     d->n = c->n;
     d->m = c->n - c->k;
@@ -378,6 +384,73 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     a.heavy = a.p.split_steps > 0 ? w->heavy : nullptr;
     const hipError_t e = orbg::launch_decode(a, st);
     if (e != hipSuccess) return fail(ORBG_EHIP, "decode launch failed: %s", hipGetErrorString(e));
+    return ORBG_OK;
+}
+
+// Mixed-code decode.
+int decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const int64_t* row_offset,
+                 const float* llr, int64_t llr_len, int64_t batch, uint64_t budget, uint8_t* codeword,
+                 int64_t codeword_len, uint64_t* queries, uint8_t* abandoned, const orbg_launch_params* params,
+                 void* stream)
+{
+    int rc = check_budget(budget, batch);
+    if (rc || (rc = check_params(params))) return rc;
+    if (llr_len < 0 || codeword_len < 0)
+        return fail(ORBG_EINVAL, "buffer lengths %lld (llr) and %lld (codeword) must not be negative",
+                    (long long)llr_len, (long long)codeword_len);
+    if (!codes || ncodes < 1 || ncodes > ORBG_MAX_CODES)
+        return fail(ORBG_EINVAL, "ncodes = %d outside [1, %d]", ncodes, ORBG_MAX_CODES);
+    if (batch > 0 && (!block_code || !row_offset || !llr || !codeword || !queries || !abandoned))
+        return fail(ORBG_EINVAL, "a device buffer is NULL");
+    CodeEntry* list[ORBG_MAX_CODES];
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (int i = 0; i < ncodes; ++i) {
+            if (codes[i] < 0 || codes[i] >= (int)g_registry.size() || !g_registry[codes[i]])
+                return fail(ORBG_EINVAL, "code id %d is not registered", codes[i]);
+            list[i] = g_registry[codes[i]];
+            if (list[i]->n > 256) return fail(ORBG_EINVAL, "mixed decodes take n <= 256 (code %d)", codes[i]);
+        }
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
+    for (int i = 0; i < ncodes; ++i)
+        if (list[i]->dev != dev) return fail(ORBG_EINVAL, "code id %d lives on another device", codes[i]);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    orbg::DecodeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.codes.ncodes = ncodes;
+    uint32_t col_base = 0, row_base = 0;
+    for (int i = 0; i < ncodes; ++i) {
+        if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i]))) return rc;
+        a.codes.c[i].row_base = row_base;
+        col_base += (uint32_t)list[i]->n;
+        row_base += (uint32_t)(a.codes.c[i].m * a.codes.c[i].nk);
+    }
+    a.codes.rwords = (int)row_base;
+    if (col_base > ORBG_MIXED_COLS)
+        return fail(ORBG_EINVAL, "the codes of one mixed decode may hold at most %d columns", ORBG_MIXED_COLS);
+    if (batch == 0) return ORBG_OK;
+    a.p = resolve_params(params, false);
+    {
+        Workspace* w = nullptr;
+        if ((rc = get_workspace(st, a.p.split_steps > 0 ? batch : 0, &w, &a.cus))) return rc;
+        a.ctrs = w->ctrs;
+        a.heavy = a.p.split_steps > 0 ? w->heavy : nullptr;
+    }
+    a.mixed = true;
+    a.block_code = block_code;
+    a.row_off = row_offset;
+    a.row_limit = llr_len < codeword_len ? llr_len : codeword_len;
+    a.llr = llr;
+    a.nblocks = batch;
+    a.budget = (uint32_t)budget;
+    a.order = nullptr;
+    a.cw = codeword;
+    a.queries = queries;
+    a.abandoned = abandoned;
+    const hipError_t e = orbg::launch_decode(a, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "mixed decode launch failed: %s", hipGetErrorString(e));
     return ORBG_OK;
 }
 
@@ -495,63 +568,13 @@ int orbg_code_release(int code_id)
 }
 
 int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const int64_t* row_offset,
-                      const float* llr, int64_t batch, uint64_t budget, uint8_t* codeword, uint64_t* queries,
-                      uint8_t* abandoned, const orbg_launch_params* params, void* stream)
+                      const float* llr, int64_t llr_len, int64_t batch, uint64_t budget, uint8_t* codeword,
+                      int64_t codeword_len, uint64_t* queries, uint8_t* abandoned, const orbg_launch_params* params,
+                      void* stream)
 {
     g_err.clear();
-    int rc = check_budget(budget, batch);
-    if (rc || (rc = check_params(params))) return rc;
-    if (!codes || ncodes < 1 || ncodes > ORBG_MAX_CODES)
-        return fail(ORBG_EINVAL, "ncodes = %d outside [1, %d]", ncodes, ORBG_MAX_CODES);
-    if (batch > 0 && (!block_code || !row_offset || !llr || !codeword || !queries || !abandoned))
-        return fail(ORBG_EINVAL, "a device buffer is NULL");
-    std::vector<CodeEntry*> list(ncodes);
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        for (int i = 0; i < ncodes; ++i) {
-            if (codes[i] < 0 || codes[i] >= (int)g_registry.size() || !g_registry[codes[i]])
-                return fail(ORBG_EINVAL, "code id %d is not registered", codes[i]);
-            list[i] = g_registry[codes[i]];
-            if (list[i]->n > 256) return fail(ORBG_EINVAL, "mixed decodes take n <= 256 (code %d)", codes[i]);
-        }
-    }
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
-    for (int i = 0; i < ncodes; ++i)
-        if (list[i]->dev != dev) return fail(ORBG_EINVAL, "code id %d lives on another device", codes[i]);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    orbg::DecodeArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.codes.ncodes = ncodes;
-    uint32_t col_base = 0, row_base = 0;
-    for (int i = 0; i < ncodes; ++i) {
-        if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i]))) return rc;
-        a.codes.c[i].row_base = row_base;
-        col_base += (uint32_t)list[i]->n;
-        row_base += (uint32_t)(a.codes.c[i].m * a.codes.c[i].nk);
-    }
-    a.codes.rwords = (int)row_base;
-    if (col_base > ORBG_MIXED_COLS)
-        return fail(ORBG_EINVAL, "the codes of one mixed decode may hold at most %d columns", ORBG_MIXED_COLS);
-    if (batch == 0) return ORBG_OK;
-    a.p = resolve_params(params, false);
-    Workspace* w = nullptr;
-    if ((rc = get_workspace(st, a.p.split_steps > 0 ? batch : 0, &w, &a.cus))) return rc;
-    a.mixed = true;
-    a.block_code = block_code;
-    a.row_off = row_offset;
-    a.llr = llr;
-    a.nblocks = batch;
-    a.budget = (uint32_t)budget;
-    a.order = nullptr;
-    a.cw = codeword;
-    a.queries = queries;
-    a.abandoned = abandoned;
-    a.ctrs = w->ctrs;
-    a.heavy = a.p.split_steps > 0 ? w->heavy : nullptr;
-    const hipError_t e = orbg::launch_decode(a, st);
-    if (e != hipSuccess) return fail(ORBG_EHIP, "mixed decode launch failed: %s", hipGetErrorString(e));
-    return ORBG_OK;
+    return decode_mixed(codes, ncodes, block_code, row_offset, llr, llr_len, batch, budget, codeword, codeword_len,
+                        queries, abandoned, params, stream);
 }
 
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)

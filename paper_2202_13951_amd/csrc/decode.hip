@@ -243,7 +243,7 @@ __device__ __forceinline__ float value_at(const float (&x)[NK], uint32_t i)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)(i % ORBG_WAVE)));
 }
 
-// 1-line fit of the sorted reliabilities (Sec. IV, eqs. (Q) and (quant) with
+// 1-line fit of the sorted reliabilities (Sec. III-E, eqs. (Q) and (quant) with
 // one segment and beta = 1): anchors at ranks 1 and h = floor(n / 2), slope
 // Q = (L_h - L_1) / (h - 1), offset J0 = [L_1 / Q] - 1 with [x] = floor(x + 1/2),
 // each operation rounded to nearest in FP32 in that order.  A slope that is not
@@ -660,7 +660,8 @@ __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (
                                           LazyState& lazy, int32_t* j0_out)
 {
     const bool left = light_block<NK, ORDERED, S, ONELINE>(x, hrow, c, cols, L, budget, split_steps, ordv,
-                                                           make_buf(cw + row, (uint32_t)c.n), queries + b,
+                                                           make_buf(cw + (row >= 0 ? row : 0), row >= 0 ? (uint32_t)c.n : 0u),
+                                                           queries + b,
                                                            abandoned + b, lazy, j0_out ? j0_out + b : nullptr);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
@@ -740,7 +741,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
              const float* __restrict__ llr, int64_t nblocks, uint32_t budget, uint32_t split_steps,
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
-             int chunk, int32_t* __restrict__ j0_out)
+             int chunk, int32_t* __restrict__ j0_out, int64_t row_limit)
 {
     // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
     // m x nk words), then their columns (sum of n entries)
@@ -795,12 +796,16 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
         return s;
     };
-    // code index and row offset of block b (wave-uniform)
+    // code index and row offset of block b (wave-uniform).  Mixed launches: a
+    // row that does not lie inside the first row_limit elements of both the LLR
+    // and the codeword buffer gets row = -1: it is read as zeros and its
+    // codeword stores are dropped (its queries and flag are still written).
     auto locate = [&](int64_t b, int& ci, int64_t& row) {
         if (MIXED) {
             ci = (int)scalar_load_u8(block_code, b);
             ci = ci < codes.ncodes ? ci : 0;          // out-of-range indices read code 0
             row = scalar_load_i64(row_off, b);
+            row = uniform_i64((row >= 0 && row <= row_limit - codes.c[ci].n) ? row : -1);
         } else {
             ci = 0;
             row = b * codes.c[0].n;
@@ -824,7 +829,8 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                 if (ok) locate(g + kk, ci, row);
                 cis[kk] = ci;
                 rows[kk] = row;
-                load_row_buf<NKMAX>(make_buf(llr + row, ok ? (uint32_t)codes.c[ci].n * 4u : 0u), xs[kk]);
+                const bool rv = ok && row >= 0;
+                load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), rv ? (uint32_t)codes.c[ci].n * 4u : 0u), xs[kk]);
                 // ordered decode: the block's first batch (every lane reads byte 0)
                 first[kk] = ORDERED ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(
                                           make_buf(order + (ok ? g + kk : 0) * 64, ok ? 1u : 0u), 0, 0, 0)
@@ -848,7 +854,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                     const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u) &&
                                       !(ONELINE && j0_out != nullptr);
                     if (done) {
-                        const buf_t cwr = make_buf(cw + rows[kk], (uint32_t)c.n);
+                        const buf_t cwr = make_buf(cw + (rows[kk] >= 0 ? rows[kk] : 0), rows[kk] >= 0 ? (uint32_t)c.n : 0u);
 #pragma unroll
                         for (int j = 0; j < NKMAX; ++j)
                             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, j * ORBG_WAVE + lane,
@@ -870,8 +876,9 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         if (b >= 0) locate(b, ci, row);
         f.ci = ci;
         f.row = row;
-        const uint32_t bytes = b >= 0 ? (uint32_t)codes.c[ci].n * 4u : 0u;
-        load_row_buf<NKMAX>(make_buf(llr + row, bytes), f.x);
+        const bool rv = b >= 0 && row >= 0;
+        const uint32_t bytes = rv ? (uint32_t)codes.c[ci].n * 4u : 0u;
+        load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), bytes), f.x);
         f.ordv = ORDERED ? load_order_buf(make_buf(order + (b >= 0 ? b : 0) * 64, b >= 0 ? 64u : 0u)) : 0u;
     };
     auto decode = [&](const RowFetch<NKMAX>& f, int64_t b) {
@@ -930,7 +937,7 @@ template <int NK, typename S, int G, bool ONELINE>
 __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __restrict__ llr_row, S* s_cols,
                                             BlockLds<S>& L, uint32_t* best, int* s_j0, uint32_t budget,
                                             uint32_t split_steps, uint8_t* __restrict__ cw_row,
-                                            uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out)
+                                            uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, bool row_ok)
 {
     const int lane = lane_id();
     const int wave = threadIdx.x / ORBG_WAVE;
@@ -941,7 +948,7 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
     float x[NK];
     bool ybit[NK];
     if (wave == 0) {
-        load_row<NK>(llr_row, n, x);
+        load_row<NK>(llr_row, row_ok ? n : 0, x);
         uint64_t hr[NK];
         load_hrows<NK>(c.rows, c.m, hr);
         const S s0 = hard_decision<NK, S>(x, n, hr, ybit);
@@ -992,7 +999,7 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
             win_lo = uniform_u32(w.x);
             win_hi = uniform_u32(w.y);
         }
-        write_codeword<NK, S>(ybit, L, win_lo, win_hi, make_buf(cw_row, (uint32_t)n));
+        write_codeword<NK, S>(ybit, L, win_lo, win_hi, make_buf(cw_row, row_ok ? (uint32_t)n : 0u));
         write_result(q_out, ab_out, found ? q : budget, !found);
     }
     __syncthreads();
@@ -1003,7 +1010,7 @@ __global__ void __launch_bounds__(G * ORBG_WAVE)
 heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int64_t* __restrict__ row_off,
              const float* __restrict__ llr, uint32_t budget, uint32_t split_steps,
              uint8_t* __restrict__ cw, uint64_t* __restrict__ queries, uint8_t* __restrict__ abandoned,
-             unsigned long long* __restrict__ ctrs, const int64_t* __restrict__ heavy)
+             unsigned long long* __restrict__ ctrs, const int64_t* __restrict__ heavy, int64_t row_limit)
 {
     __shared__ S s_cols[ORBG_WAVE * NKMAX];
     __shared__ BlockLds<S> L;
@@ -1023,21 +1030,24 @@ heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         int ci = MIXED ? (int)uniform_u32(block_code[b]) : 0;
         ci = ci < codes.ncodes ? ci : 0;
         const CodeDesc& c = codes.c[ci];
-        const int64_t row = MIXED ? uniform_i64(row_off[b]) : b * c.n;
+        int64_t row = MIXED ? uniform_i64(row_off[b]) : b * c.n;
+        // as in the light pass: a row outside the buffers is read as zeros, its stores dropped
+        const bool row_ok = !MIXED || (row >= 0 && row <= row_limit - c.n);
+        row = row_ok ? row : 0;
         if (c.nk == 1 || NKMAX == 1) {
             heavy_block<1, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
-                                 abandoned + b);
+                                 abandoned + b, row_ok);
         } else if (c.nk == 2 || NKMAX == 2) {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
             heavy_block<K2, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
-                                  abandoned + b);
+                                  abandoned + b, row_ok);
         } else if (c.nk == 4 || NKMAX == 4) {
             constexpr int K4 = NKMAX >= 4 ? 4 : 1;
             heavy_block<K4, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
-                                  abandoned + b);
+                                  abandoned + b, row_ok);
         } else {
             heavy_block<NKMAX, S, G, ONELINE>(c, llr + row, s_cols, L, &best, &s_j0, budget, split_steps, cw + row, queries + b,
-                                     abandoned + b);
+                                     abandoned + b, row_ok);
         }
     }
 }
@@ -1058,7 +1068,7 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
     const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
     light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
-        a.abandoned, a.ctrs, a.heavy, chunk, a.j0);
+        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit);
 }
 
 template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
@@ -1066,7 +1076,8 @@ static void launch_heavy_g(const DecodeArgs& a, uint32_t split, hipStream_t stre
 {
     const int64_t wgs = (int64_t)a.cus * (a.p.heavy_wg_per_cu > 0 ? a.p.heavy_wg_per_cu : 2);
     heavy_kernel<NKMAX, S, MIXED, G, ONELINE><<<(unsigned)wgs, G * ORBG_WAVE, 0, stream>>>(
-        a.codes, a.block_code, a.row_off, a.llr, a.budget, split, a.cw, a.queries, a.abandoned, a.ctrs, a.heavy);
+        a.codes, a.block_code, a.row_off, a.llr, a.budget, split, a.cw, a.queries, a.abandoned, a.ctrs, a.heavy,
+        a.row_limit);
 }
 
 template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE = false>

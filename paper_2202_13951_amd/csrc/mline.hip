@@ -1,4 +1,4 @@
-// Full (m-line) ORBGRAND decode kernel for gfx950 (Sec. IV).
+// Full (m-line) ORBGRAND decode kernel for gfx950 (Sec. III-D; fit of Sec. III-E).
 //
 // Per block, one wave:
 //   1. the LLR row (n <= 256: up to four elements per lane), hard decision and

@@ -45,6 +45,7 @@ struct DecodeArgs {
     bool mixed;                // per-block code index and row offsets given
     const uint8_t* block_code; // device, nblocks (mixed)
     const int64_t* row_off;    // device, nblocks: element offset of the row in llr and codeword (mixed)
+    int64_t row_limit;         // mixed: rows must end within this many elements of llr and codeword
     const float* llr;
     int64_t nblocks;
     uint32_t budget;

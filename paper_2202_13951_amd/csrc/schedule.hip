@@ -258,7 +258,7 @@ int orbg_unpack_schedule(const Schedule* s, uint64_t count, uint8_t* d_out, hipS
 
 // ---------------------------------------------------------------------------
 // 1-line ORBGRAND schedules.  With one segment of slope beta = 1 and offset J0
-// (Sec. IV, eqs. (relest_seg) and (quant) with m = 1), the reliability weight
+// (Sec. III-D eq. (relest_seg) and Sec. III-E eq. (quant) with m = 1), the reliability weight
 // of a pattern of Hamming weight w and logistic weight W is J0 w + W
 // (eq. (W2IJ)), so the 1-line order takes the same (W, w) classes as the basic
 // order, each still in Landslide (lexicographic) order, but sorted by

@@ -60,12 +60,75 @@ def test_launch_params_are_checked(field, value, msg):
 def test_mixed_rejects_unregistered_and_bad_counts():
     L = binding.load()
     ids = (ctypes.c_int * 1)(12345)
-    rc = L.orbg_decode_mixed(ids, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), 1, 100,
-                             ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), None, None)
+    p = ctypes.c_void_p(8)
+    rc = L.orbg_decode_mixed(ids, 1, p, p, p, 1000, 1, 100, p, 1000, p, p, None, None)
     assert rc == -1 and "not registered" in L.orbg_last_error().decode()
-    rc = L.orbg_decode_mixed(ids, 9, None, None, None, 0, 100, None, None, None, None, None)
+    rc = L.orbg_decode_mixed(ids, 9, None, None, None, 0, 0, 100, None, 0, None, None, None, None)
     assert rc == -1 and "ncodes" in L.orbg_last_error().decode()
     assert L.orbg_code_release(777) == -1
+
+
+@pytest.mark.parametrize("llr_len,cw_len", [(-1, 100), (100, -5), (-1, -1)])
+def test_mixed_rejects_negative_buffer_lengths(llr_len, cw_len):
+    """The mixed decode bounds every row by the two buffer lengths it is given;
+    negative lengths are rejected before anything is looked up or launched."""
+    L = binding.load()
+    ids = (ctypes.c_int * 1)(0)
+    p = ctypes.c_void_p(8)
+    rc = L.orbg_decode_mixed(ids, 1, p, p, p, llr_len, 1, 100, p, cw_len, p, p, None, None)
+    assert rc == -1 and "must not be negative" in L.orbg_last_error().decode()
+
+
+def _cpu(shape, dtype):
+    import torch
+    return torch.zeros(shape, dtype=dtype)
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("block_code_dtype", "block_code must be torch.uint8"),
+    ("row_offset_dtype", "row_offset must be torch.int64"),
+    ("row_offset_len", "row_offset has shape"),
+    ("llr_dtype", "llr must be torch.float32"),
+    ("llr_rank", "llr must have 1 dimension"),
+    ("codeword_dtype", "codeword must be torch.uint8"),
+    ("queries_dtype", "queries must be torch.int64"),
+    ("abandoned_len", "abandoned has shape"),
+    ("host_tensors", "must be on a CUDA device"),
+])
+def test_binding_mixed_rejects_bad_tensors(case, msg):
+    """The binding checks dtype, rank, shape, contiguity and device of every tensor
+    (ValueError, independent of python -O) before it calls the library."""
+    import torch
+    N = 4
+    t = dict(block_code=_cpu(N, torch.uint8), row_offset=_cpu(N, torch.int64), llr=_cpu(64, torch.float32),
+             codeword=_cpu(64, torch.uint8), queries=_cpu(N, torch.int64), abandoned=_cpu(N, torch.uint8))
+    field, what = case.rsplit("_", 1) if case != "host_tensors" else ("", "")
+    if what == "dtype":
+        t[field] = t[field].to(torch.int32 if t[field].dtype != torch.int32 else torch.int64)
+    elif what == "len":
+        t[field] = t[field][:N - 1]
+    elif what == "rank":
+        t[field] = t[field].reshape(8, 8)
+    with pytest.raises(ValueError, match=msg):
+        binding.orbg_decode_mixed([0], t["block_code"], t["row_offset"], t["llr"], 100, t["codeword"], t["queries"],
+                                  t["abandoned"])
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("llr_dtype", "llr must be torch.float32"), ("llr_width", r"llr has shape \(4, 31\), expected \(4, 32\)"),
+    ("llr_rank", "llr must be a 2-D"), ("host", "must be on a CUDA device")])
+def test_binding_decode_rejects_bad_tensors(case, msg):
+    import torch
+    H = np.zeros((6, 32), dtype=np.uint8)
+    llr = _cpu((4, 32), torch.float32)
+    if case == "llr_dtype":
+        llr = llr.double()
+    elif case == "llr_width":
+        llr = _cpu((4, 31), torch.float32)
+    elif case == "llr_rank":
+        llr = _cpu(128, torch.float32)
+    with pytest.raises(ValueError, match=msg):
+        binding.orbg_decode(H, llr, 100)
 
 
 @pytest.mark.parametrize("n,k,budget,bufs,msg", [

@@ -1,4 +1,4 @@
-"""GPU parity of 1-line ORBGRAND (Sec. IV with one segment): the device schedules
+"""GPU parity of 1-line ORBGRAND (Sec. III-D/III-E with one segment): the device schedules
 against the oracle's order for every offset class, and the HIP decoder against the
 oracle decoder bit for bit -- codeword, query count, abandon flag and the fitted
 offset J0 -- on the same seeded inputs."""

@@ -218,3 +218,53 @@ def test_stream_code_set_matches_oracle(gpu_device, shape):
         assert (_rows(cwn, ron, n, idx) == ocw).all(), STREAM_NAMES[ci]
         assert (qn[idx] == oq).all(), STREAM_NAMES[ci]
         assert (abn[idx] == oab).all(), STREAM_NAMES[ci]
+
+
+def test_rows_outside_the_buffers_read_zeros_and_store_nothing(gpu_device):
+    """A mixed decode bounds every row by the LLR and codeword lengths it is
+    given: a row with a negative offset, or one that would run past either
+    buffer, is decoded from zeros (query 1, not abandoned) and leaves the
+    codeword buffer untouched; the other blocks decode as usual."""
+    print("mixed rows outside the buffers", flush=True)
+    N, budget = 600, 10 ** 4
+    HG, ids, llr, bc, ro, t = _setup(N, 4.0, 21, gpu_device)
+    bad = {5: -3, 17: llr.size - 10, 40: -(1 << 40), 41: (1 << 40)}
+    ro_bad = ro.copy()
+    for i, v in bad.items():
+        ro_bad[i] = v
+    t_bad = dict(t, ro=torch.from_numpy(ro_bad).to(gpu_device))
+    ref = _run_mixed(ids, t, N, budget)
+    dev = gpu_device
+    cw = torch.full((llr.size,), 7, dtype=torch.uint8, device=dev)
+    q = torch.zeros(N, dtype=torch.int64, device=dev)
+    ab = torch.full((N,), 9, dtype=torch.uint8, device=dev)
+    binding.orbg_decode_mixed(ids, t_bad["bc"], t_bad["ro"], t["llr"], budget, cw, q, ab)
+    torch.cuda.synchronize()
+    cwn, qn, abn = cw.cpu().numpy(), q.cpu().numpy(), ab.cpu().numpy()
+    good = np.array([i for i in range(N) if i not in bad])
+    for ci, (H, G) in enumerate(HG):
+        n = H.shape[1]
+        idx = good[bc[good] == ci]
+        assert (_rows(cwn, ro, n, idx) == _rows(ref[0], ro, n, idx)).all()
+    assert (qn[good].astype(np.uint64) == ref[1][good]).all() and (abn[good] == ref[2][good]).all()
+    for i in bad:
+        assert qn[i] == 1 and abn[i] == 0, i
+    # every byte not inside a good block's row still holds the fill value
+    touched = np.zeros(llr.size, dtype=bool)
+    for i in good:
+        touched[ro[i]:ro[i] + HG[bc[i]][0].shape[1]] = True
+    assert (cwn[~touched] == 7).all()
+
+
+def test_binding_rejects_bad_output_tensors(gpu_device):
+    H, _ = codes.code("rlc32_26")
+    llr = torch.zeros((4, 32), dtype=torch.float32, device=gpu_device)
+    bad = [(torch.zeros((4, 32), dtype=torch.uint8, device=gpu_device), torch.zeros(4, dtype=torch.int32,
+            device=gpu_device), torch.zeros(4, dtype=torch.uint8, device=gpu_device)),
+           (torch.zeros((4, 31), dtype=torch.uint8, device=gpu_device), torch.zeros(4, dtype=torch.int64,
+            device=gpu_device), torch.zeros(4, dtype=torch.uint8, device=gpu_device)),
+           (torch.zeros((4, 32), dtype=torch.uint8), torch.zeros(4, dtype=torch.int64),
+            torch.zeros(4, dtype=torch.uint8))]
+    for out in bad:
+        with pytest.raises(ValueError):
+            binding.orbg_decode(H, llr, 100, out=out)

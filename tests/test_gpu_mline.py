@@ -1,4 +1,4 @@
-"""GPU parity of full (m-line) ORBGRAND (Sec. IV): the HIP decoder against the
+"""GPU parity of full (m-line) ORBGRAND (Sec. III-D, III-E): the HIP decoder against the
 oracle decoder bit for bit -- codeword, query count, abandon flag and the number
 of segments the fit used -- on the same seeded inputs, for one to four segments,
 with and without the J/beta rounding."""

@@ -1,4 +1,4 @@
-"""Pins of the 1-line ORBGRAND oracle (the full ORBGRAND of Sec. IV with one
+"""Pins of the 1-line ORBGRAND oracle (the full ORBGRAND of Sec. III-D with one
 segment): the order against brute-force sorting of all subsets by the
 reliability weight J0 w + W of eq. (W2IJ) (beta = 1), the J0 = 0 reduction to
 the basic order and decoder, the fit of eqs. (Q) and (quant) on curves whose J0

@@ -1,4 +1,4 @@
-"""Pins of the full (m-line) ORBGRAND oracle of Sec. IV: the order against a
+"""Pins of the full (m-line) ORBGRAND oracle of Sec. III-D/III-E: the order against a
 brute-force sort of all subsets by the key the section fixes (reliability
 weight of eq. (W2IJ), then the split pattern in the nested-loop order of the
 integer splitting algorithm, then the Cartesian product of eq. (cartP) with
