@@ -205,6 +205,28 @@ int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code,
                       uint64_t budget, uint8_t* codeword, int64_t codeword_len, uint64_t* queries,
                       uint8_t* abandoned, const orbg_launch_params* params, void* stream);
 
+/*
+ * orbg_decode_mixed for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, layouts, rules and results, but the call allocates nothing.
+ * Its work counters and heavy-block list live in a fixed array of the library
+ * (about 2.1 MB per device, held until the process ends), so:
+ *   - batch <= ORBG_NOALLOC_BATCH_MAX (262,144 blocks); larger batches return
+ *     ORBG_EINVAL;
+ *   - every code must be registered and its query schedule for this budget
+ *     must exist: one orbg_decode_mixed call with the same codes and budget
+ *     builds them (otherwise ORBG_EINVAL, nothing launched);
+ *   - all calls on one device share that array: calls that overlap in time on
+ *     one device (different streams, or host threads) race and may return wrong
+ *     results; calls in one stream are ordered and safe.  The counters are
+ *     cleared by a kernel at the start of every call.
+ */
+#define ORBG_NOALLOC_BATCH_MAX 262144
+int orbg_decode_mixed_noalloc(const int* codes, int ncodes, const uint8_t* block_code,
+                              const int64_t* row_offset, const float* llr, int64_t llr_len,
+                              int64_t batch, uint64_t budget, uint8_t* codeword, int64_t codeword_len,
+                              uint64_t* queries, uint8_t* abandoned, const orbg_launch_params* params,
+                              void* stream);
 
 /*
  * Copies the first `count` entries of the library's basic-ORBGRAND query

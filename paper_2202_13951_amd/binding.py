@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liborbgrand.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "orbgrand.h")
 
 ORBG_OK = 0
+ORBG_NOALLOC_BATCH_MAX = 262144     # largest batch of orbg_decode_mixed_noalloc
 _lib = None
 
 
@@ -59,6 +60,8 @@ def load():
     L.orbg_code_release.restype = ci
     L.orbg_decode_mixed.argtypes = [vp, ci, vp, vp, vp, i64, i64, u64, vp, i64, vp, vp, vp, vp]
     L.orbg_decode_mixed.restype = ci
+    L.orbg_decode_mixed_noalloc.argtypes = [vp, ci, vp, vp, vp, i64, i64, u64, vp, i64, vp, vp, vp, vp]
+    L.orbg_decode_mixed_noalloc.restype = ci
     L.orbg_mlp_workspace_bytes.argtypes = [i64]
     L.orbg_mlp_workspace_bytes.restype = i64
     L.orbg_mlp_features.argtypes = [vp, ci, i64, vp, vp]
@@ -298,6 +301,31 @@ def orbg_decode_mixed(code_ids, block_code, row_offset, llr, budget: int, codewo
                                   codeword.numel(), ctypes.c_void_p(queries.data_ptr()),
                                   ctypes.c_void_p(abandoned.data_ptr()), _params_ptr(params), _stream_ptr(stream))
     _check("orbg_decode_mixed", rc)
+
+
+def orbg_decode_mixed_noalloc(code_ids, block_code, row_offset, llr, budget: int, codeword, queries, abandoned,
+                              params: LaunchParams | None = None, stream=None):
+    """orbg_decode_mixed without any device allocation (batch <= 262144; the codes'
+    schedules for this budget must exist; calls overlapping on one device race)."""
+    import torch
+    ids = (ctypes.c_int * len(code_ids))(*[int(c) for c in code_ids])
+    _tensor_spec(block_code, "block_code", torch.uint8, ndim=1)
+    N = block_code.shape[0]
+    spec = [(row_offset, "row_offset", torch.int64, (N,), None), (llr, "llr", torch.float32, None, 1),
+            (codeword, "codeword", torch.uint8, None, 1), (queries, "queries", torch.int64, (N,), None),
+            (abandoned, "abandoned", torch.uint8, (N,), None)]
+    for t, name, dt, shape, nd in spec:
+        _tensor_spec(t, name, dt, shape, nd)
+    _on_device(block_code, "block_code")
+    for t, name, *_ in spec:
+        _on_device(t, name, block_code.device)
+    rc = load().orbg_decode_mixed_noalloc(ids, len(code_ids), ctypes.c_void_p(block_code.data_ptr()),
+                                          ctypes.c_void_p(row_offset.data_ptr()), ctypes.c_void_p(llr.data_ptr()),
+                                          llr.numel(), N, int(budget), ctypes.c_void_p(codeword.data_ptr()),
+                                          codeword.numel(), ctypes.c_void_p(queries.data_ptr()),
+                                          ctypes.c_void_p(abandoned.data_ptr()), _params_ptr(params),
+                                          _stream_ptr(stream))
+    _check("orbg_decode_mixed_noalloc", rc)
 
 
 def orbg_schedule_export(n: int, count: int, stream=None) -> np.ndarray:

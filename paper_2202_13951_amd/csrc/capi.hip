@@ -346,6 +346,43 @@ int get_ml_table(hipStream_t st, const uint32_t** out)
     return ORBG_OK;
 }
 
+// Scratch of the allocation-free mixed decode: the work counters (ORBG_CTR_WORDS
+// words), then the heavy-block list (one i64 per block).  Each device holds its
+// own copy for the life of the process; calls on one device share it.
+static_assert(ORBG_NOALLOC_BATCH_MAX == (1 << 18), "scratch size");
+static __device__ __align__(256) unsigned long long scratch[ORBG_CTR_WORDS + ORBG_NOALLOC_BATCH_MAX];
+
+// device -> device address of `scratch` on it (the host-side name is only a
+// stand-in for the symbol: kernels get this address)
+std::map<int, unsigned long long*> g_scratch;
+
+int get_scratch(int dev, unsigned long long** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) { *out = it->second; return ORBG_OK; }
+    unsigned long long* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return fail(ORBG_EHIP, "cannot find the scratch array on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch.emplace(dev, ptr);
+    *out = ptr;
+    return ORBG_OK;
+}
+
+int compute_units(int dev, int* cus)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto c = g_cus.find(dev);
+    if (c == g_cus.end()) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1) v = 256;
+        c = g_cus.emplace(dev, v).first;
+    }
+    *cus = c->second;
+    return ORBG_OK;
+}
+
 int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
                   const orbg_launch_params* params, void* stream, bool oneline = false, int32_t* j0 = nullptr)
@@ -387,17 +424,22 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     return ORBG_OK;
 }
 
-// Mixed-code decode.
+// Mixed-code decode.  noalloc: no device allocation of any kind -- the
+// schedules must exist already, and the work counters and heavy-block list
+// live in this device's `scratch` array (batch <= ORBG_NOALLOC_BATCH_MAX).
 int decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const int64_t* row_offset,
                  const float* llr, int64_t llr_len, int64_t batch, uint64_t budget, uint8_t* codeword,
                  int64_t codeword_len, uint64_t* queries, uint8_t* abandoned, const orbg_launch_params* params,
-                 void* stream)
+                 void* stream, bool noalloc)
 {
     int rc = check_budget(budget, batch);
     if (rc || (rc = check_params(params))) return rc;
     if (llr_len < 0 || codeword_len < 0)
         return fail(ORBG_EINVAL, "buffer lengths %lld (llr) and %lld (codeword) must not be negative",
                     (long long)llr_len, (long long)codeword_len);
+    if (noalloc && batch > ORBG_NOALLOC_BATCH_MAX)
+        return fail(ORBG_EINVAL, "batch = %lld above %d, the most the allocation-free decode takes",
+                    (long long)batch, ORBG_NOALLOC_BATCH_MAX);
     if (!codes || ncodes < 1 || ncodes > ORBG_MAX_CODES)
         return fail(ORBG_EINVAL, "ncodes = %d outside [1, %d]", ncodes, ORBG_MAX_CODES);
     if (batch > 0 && (!block_code || !row_offset || !llr || !codeword || !queries || !abandoned))
@@ -422,7 +464,7 @@ int decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const 
     a.codes.ncodes = ncodes;
     uint32_t col_base = 0, row_base = 0;
     for (int i = 0; i < ncodes; ++i) {
-        if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i]))) return rc;
+        if ((rc = describe(list[i], budget, st, col_base, &a.codes.c[i], !noalloc))) return rc;
         a.codes.c[i].row_base = row_base;
         col_base += (uint32_t)list[i]->n;
         row_base += (uint32_t)(a.codes.c[i].m * a.codes.c[i].nk);
@@ -430,9 +472,15 @@ int decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, const 
     a.codes.rwords = (int)row_base;
     if (col_base > ORBG_MIXED_COLS)
         return fail(ORBG_EINVAL, "the codes of one mixed decode may hold at most %d columns", ORBG_MIXED_COLS);
+    unsigned long long* scr = nullptr;
+    if (noalloc && (rc = get_scratch(dev, &scr))) return rc;
     if (batch == 0) return ORBG_OK;
     a.p = resolve_params(params, false);
-    {
+    if (noalloc) {
+        if ((rc = compute_units(dev, &a.cus))) return rc;
+        a.ctrs = scr;
+        a.heavy = a.p.split_steps > 0 ? reinterpret_cast<int64_t*>(scr + ORBG_CTR_WORDS) : nullptr;
+    } else {
         Workspace* w = nullptr;
         if ((rc = get_workspace(st, a.p.split_steps > 0 ? batch : 0, &w, &a.cus))) return rc;
         a.ctrs = w->ctrs;
@@ -574,7 +622,17 @@ int orbg_decode_mixed(const int* codes, int ncodes, const uint8_t* block_code, c
 {
     g_err.clear();
     return decode_mixed(codes, ncodes, block_code, row_offset, llr, llr_len, batch, budget, codeword, codeword_len,
-                        queries, abandoned, params, stream);
+                        queries, abandoned, params, stream, false);
+}
+
+int orbg_decode_mixed_noalloc(const int* codes, int ncodes, const uint8_t* block_code, const int64_t* row_offset,
+                              const float* llr, int64_t llr_len, int64_t batch, uint64_t budget, uint8_t* codeword,
+                              int64_t codeword_len, uint64_t* queries, uint8_t* abandoned,
+                              const orbg_launch_params* params, void* stream)
+{
+    g_err.clear();
+    return decode_mixed(codes, ncodes, block_code, row_offset, llr, llr_len, batch, budget, codeword, codeword_len,
+                        queries, abandoned, params, stream, true);
 }
 
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream)
