@@ -162,7 +162,8 @@ def query_breakdown(q, ab, err, budget, sweep=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 
 # Sources the basic and 1-line decode kernels (light and heavy pass, schedules,
 # launch) are compiled from, and those of the m-line kernel: committed HBM
 # counters stay valid while these are unchanged.
-DECODE_SOURCES = ("decode.hip", "orbg_device.h", "orbg_internal.h", "orbg_kernels.h", "schedule.hip")
+DECODE_SOURCES = ("decode.hip", "decode_impl.h", "decode_nk1.hip", "decode_nk2.hip", "decode_nk4.hip", "decode_nk8.hip",
+                  "decode_nk16.hip", "orbg_device.h", "orbg_internal.h", "orbg_kernels.h", "schedule.hip")
 MLINE_SOURCES = ("mline.hip", "orbg_mline.h", "orbg_device.h", "orbg_internal.h")
 
 
