@@ -1053,7 +1053,7 @@ heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     }
 }
 
-__global__ void reset_counters_kernel(unsigned long long* c)
+static __global__ void reset_counters_kernel(unsigned long long* c)
 {
     for (int i = threadIdx.x; i < ORBG_CTR_WORDS; i += blockDim.x) c[i] = 0ull;
 }
