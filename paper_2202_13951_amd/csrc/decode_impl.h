@@ -422,6 +422,23 @@ __device__ __forceinline__ int rank_and_tables(const float (&x)[NK], int n, cons
 // ranks hold rank 0, whose column is zero: the low-rank table and the first
 // three slots are read together (one LDS round trip), the last four only when
 // some lane's entry has more than three ranks above 8 (a ballot).
+// a ^ b ^ c in one instruction (gfx950's three-input bit operation; the
+// truth table of a three-way XOR is 0x96).
+template <typename S>
+__device__ __forceinline__ S xor3(S a, S b, S c);
+template <>
+__device__ __forceinline__ uint32_t xor3<uint32_t>(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+template <>
+__device__ __forceinline__ uint64_t xor3<uint64_t>(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename S>
 __device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
 {
@@ -429,9 +446,12 @@ __device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
     const S v1 = L.h[(ent.x >> 8) & 0xffu];
     const S v2 = L.h[(ent.x >> 16) & 0xffu];
     const S v3 = L.h[ent.x >> 24];
-    S v = v0 ^ v1 ^ v2 ^ v3;
-    if (ballot(ent.y != 0u) != 0ull)
-        v ^= L.h[ent.y & 0xffu] ^ L.h[(ent.y >> 8) & 0xffu] ^ L.h[(ent.y >> 16) & 0xffu] ^ L.h[ent.y >> 24];
+    S v = xor3<S>(v0, v1, v2) ^ v3;
+    if (ballot(ent.y != 0u) != 0ull) {
+        const S w0 = L.h[ent.y & 0xffu], w1 = L.h[(ent.y >> 8) & 0xffu];
+        const S w2 = L.h[(ent.y >> 16) & 0xffu], w3 = L.h[ent.y >> 24];
+        v = xor3<S>(xor3<S>(v, w0, w1), w2, w3);
+    }
     return v;
 }
 
