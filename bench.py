@@ -67,8 +67,10 @@ WORKLOADS = {
     "learned": dict(code="rlc128_105", n=128, k=105, train_pairs=10 ** 7, train_ebn0=(3.0, 5.0),
                     ebn0=[3.0, 3.5, 4.0, 4.5, 5.0], blocks=10 ** 6, budget=10 ** 6, epochs=2, batch=8192, lr=2e-3,
                     desc="RLC(128,105) H=[P|I23]: BF16 MLP 128-256-256-64 trained on 1e7 decoder-generated pairs "
-                         "at Eb/N0 ~ U[3,5] dB, reorders the first 64 pattern batches; plain vs learned ORBGRAND "
-                         "on 1e6 held-out blocks per point at 3..5 dB, budget 1e6"),
+                         "at Eb/N0 ~ U[3,5] dB (blocks whose first hit lies in batches 1..63), gated decode: batch 0 "
+                         "for every block, the network orders batches 1..63 only for blocks batch 0 does not decide, "
+                         "ORBGRAND fallback after 64 batches; plain vs learned vs the fixed prior order on 1e6 "
+                         "held-out blocks per point at 3..5 dB, budget 1e6"),
     "stream": dict(codes=["rlc64_52", "bch127_113", "rlc128_116", "rlc256_240"], ratio=[1, 1, 1, 1],
                    ebn0_range=(3.0, 6.0), rates=[1e5, 1e6], seconds=1.0, budget=10 ** 5,
                    capacity=1 << 16, max_batch=1 << 13, streams=8,
@@ -718,8 +720,10 @@ def run_stream(args, wl, dev):
 
 
 def run_learned(args, wl, dev):
-    """Train the proposal on decoder-generated pairs, then plain vs learned on
-    held-out blocks (same blocks for both arms)."""
+    """Train the proposal on decoder-generated pairs (blocks whose first hit lies
+    past batch 0, the ones the gated decode asks the network about), then plain,
+    gated learned and the fixed prior order on the same held-out blocks, with a
+    cost breakdown of the gated decode's stages."""
     import torch
     from paper_2202_13951_amd import binding, learned
     from synth import channel, codes
@@ -728,10 +732,10 @@ def run_learned(args, wl, dev):
     t0 = time.perf_counter()
     xs, ys, seen, i = [], [], 0, 0
     while sum(int(x.shape[0]) for x in xs) < wl["train_pairs"]:
-        x, y = learned.generate_pairs(H, G, 1 << 21, *wl["train_ebn0"], seed=10 + i, device=dev)
+        x, y = learned.generate_pairs(H, G, 1 << 22, *wl["train_ebn0"], seed=10 + i, device=dev, gated=True)
         xs.append(x)
         ys.append(y)
-        seen += 1 << 21
+        seen += 1 << 22
         i += 1
     x = torch.cat(xs)[: wl["train_pairs"]].contiguous()
     y = torch.cat(ys)[: wl["train_pairs"]].contiguous()
@@ -744,58 +748,105 @@ def run_learned(args, wl, dev):
                            log=lambda m: print(m, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    label_hist = torch.bincount(y.long(), minlength=64)[:8].cpu().tolist()
+    hist = torch.bincount(y.long(), minlength=64)[:64].cpu().numpy().astype(np.float64)
+    pl = hist[hist > 0] / hist.sum()
+    label_entropy = float(-(pl * np.log(pl)).sum())
+    prior = learned.prior_order(y, dev)
     del x, y
 
     def timed(fn):
-        out = []
-        ms = time_calls(lambda: out.append(fn()), stream)
-        return out[0], ms / 1e3
+        out = [fn()]                                  # untimed: work spaces reach their size here
+        torch.cuda.synchronize()
+        ms = time_calls(lambda: out.append(fn()), stream, reps=3)
+        return out[-1], ms / 1e3
 
+    shapes = {"defaults": None, "no_heavy_pass": binding.LaunchParams(split_steps=0)}
     points = {}
-    tot = dict(blocks=0, plain_s=0.0, learned_s=0.0, plain_q=0, learned_q=0)
+    tot = {k: dict(plain_s=0.0, learned_s=0.0) for k in shapes}
+    tot_q = dict(blocks=0, plain=0.0, learned=0.0, prior=0.0)
+    flops_fwd = 2.0 * (128 * 256 + 256 * 256 + 256 * 64)
+    fwd_t, fwd_rows = 0.0, 0
     for e in wl["ebn0"]:
         llr, sent = channel.awgn_llr_torch(G, wl["blocks"], e, seed=5000 + int(round(e * 10)), device=dev)
+        N = wl["blocks"]
         binding.orbg_decode(H, llr[:1024], wl["budget"])                    # warm caches
-        learned.decode_learned(prop, H, llr[:1024], wl["budget"])
-        (pc, pq, pab), pt = timed(lambda: binding.orbg_decode(H, llr, wl["budget"]))
-        (lc, lq, lab), lt = timed(lambda: learned.decode_learned(prop, H, llr, wl["budget"]))
+        learned.decode_learned_gated(prop, H, llr[:1024], wl["budget"])
+        pt = {}
+        for name, P in shapes.items():
+            (pc, pq, pab), pt[name] = timed(lambda: binding.orbg_decode_ex(H, llr, wl["budget"], params=P))
+        lt = {}
+        for name, P in shapes.items():
+            (lc, lq, lab, rest), lt[name] = timed(lambda: learned.decode_learned_gated(prop, H, llr, wl["budget"],
+                                                                                      params=P))
+        po = prior.unsqueeze(0).expand(N, 64).contiguous()
+        rc_, rq, rab = binding.orbg_decode_ordered(H, llr, wl["budget"], po)
+        # stages of the gated decode, each timed on its own (default shape)
+        _, t_first = timed(lambda: binding.orbg_decode(H, llr, 64))
+        idx = torch.nonzero(pq > 64).flatten()
+        sub = llr[idx].contiguous()
+        (xf,), t_feat = timed(lambda: (learned.features(sub),))
+        lg, t_fwd = timed(lambda: prop.logits(xf))
+        if idx.numel():
+            fwd_t += t_fwd
+            fwd_rows += int(idx.numel())
+        lgp = lg.clone()
+        lgp[:, 0] = float("inf")
+        ordr = torch.empty((idx.numel(), 64), dtype=torch.uint8, device=dev)
+        _, t_ord = timed(lambda: binding.orbg_mlp_order(lgp, ordr))
+        _, t_rest = timed(lambda: binding.orbg_decode_ordered(H, sub, wl["budget"], ordr))
         pe = (pc != sent).any(dim=1).cpu().numpy()
         le = (lc != sent).any(dim=1).cpu().numpy()
-        pqn, lqn = pq.cpu().numpy().astype(np.float64), lq.cpu().numpy().astype(np.float64)
+        re_ = (rc_ != sent).any(dim=1).cpu().numpy()
+        pqn, lqn, rqn = (t.cpu().numpy().astype(np.float64) for t in (pq, lq, rq))
         mu, ci = learned.paired_ci(lqn - pqn)
-        pre = pqn <= learned.PREFIX
-        N = wl["blocks"]
+        mur, cir = learned.paired_ci(lqn - rqn)
         points[f"{e:.1f}"] = {
             "bler_plain": float(pe.mean()), "bler_plain_ci95": list(wilson(int(pe.sum()), N)),
             "bler_learned": float(le.mean()), "bler_learned_ci95": list(wilson(int(le.sum()), N)),
+            "bler_prior": float(re_.mean()),
             "bler_diff_ci95": list(learned.paired_ci(le.astype(np.float64) - pe.astype(np.float64))[1]),
             "mean_queries_plain": float(pqn.mean()), "mean_queries_learned": float(lqn.mean()),
-            "queries_diff_mean": mu, "queries_diff_ci95": list(ci),
-            "mean_queries_prefix_blocks_plain": float(pqn[pre].mean()),
-            "mean_queries_prefix_blocks_learned": float(lqn[pre].mean()),
-            "blocks_per_s_plain": N / pt, "blocks_per_s_learned": N / lt,
+            "mean_queries_prior_order": float(rqn.mean()),
+            "queries_diff_vs_plain": mu, "queries_diff_vs_plain_ci95": list(ci),
+            "queries_diff_vs_prior": mur, "queries_diff_vs_prior_ci95": list(cir),
+            "blocks_network_ran_on": int(rest),
+            "blocks_per_s_plain": {k: N / v for k, v in pt.items()},
+            "blocks_per_s_learned": {k: N / v for k, v in lt.items()},
+            "stage_ms": {"plain_decode": pt["defaults"] * 1e3, "first_batch_pass": t_first * 1e3,
+                         "features": t_feat * 1e3, "network_forward": t_fwd * 1e3, "order": t_ord * 1e3,
+                         "ordered_search_of_listed": t_rest * 1e3, "gated_total": lt["defaults"] * 1e3},
             "abandoned_plain": int(pab.sum()), "abandoned_learned": int(lab.sum())}
         print(f"learned {e} dB: {points[f'{e:.1f}']}", file=sys.stderr, flush=True)
-        tot["blocks"] += N
-        tot["plain_s"] += pt
-        tot["learned_s"] += lt
-        tot["plain_q"] += float(pqn.sum())
-        tot["learned_q"] += float(lqn.sum())
-        del llr, sent, pc, pq, pab, lc, lq, lab
+        tot_q["blocks"] += N
+        tot_q["plain"] += float(pqn.sum())
+        tot_q["learned"] += float(lqn.sum())
+        tot_q["prior"] += float(rqn.sum())
+        for k in shapes:
+            tot[k]["plain_s"] += pt[k]
+            tot[k]["learned_s"] += lt[k]
+        del llr, sent, pc, pq, pab, lc, lq, lab, rc_, rq, rab, sub, xf, lg, lgp, ordr
         torch.cuda.empty_cache()
+    Nt = tot_q["blocks"]
+    mfma = (flops_fwd * fwd_rows / fwd_t) if fwd_t > 0 else 0.0
     return {
-        "metric": METRIC, "value": tot["blocks"] / tot["learned_s"], "unit": "blocks/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": tot["learned_s"] * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64 (decode), bf16/fp32 (network)", "data": "synthetic",
+        "metric": METRIC, "value": Nt / tot["defaults"]["learned_s"], "unit": "blocks/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": tot["defaults"]["learned_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 syndromes / FP32 LLR (decode), bf16 MFMA with fp32 "
+                                                      "accumulation (network)", "data": "synthetic",
         "config": {"workload": wl["desc"], "code": wl["code"], "ebn0_db": wl["ebn0"],
                    "blocks_per_point": wl["blocks"], "budget": wl["budget"], "train_pairs": wl["train_pairs"],
                    "train_ebn0_db": list(wl["train_ebn0"]), "epochs": wl["epochs"], "minibatch": wl["batch"],
-                   "lr": wl["lr"]},
-        "plain_value": tot["blocks"] / tot["plain_s"],
-        "mean_queries_plain": tot["plain_q"] / tot["blocks"], "mean_queries_learned": tot["learned_q"] / tot["blocks"],
+                   "lr": wl["lr"], "form": "gated: network only for blocks the first 64 queries do not decide"},
+        "plain_value": Nt / tot["defaults"]["plain_s"],
+        "by_launch_shape": {k: {"plain_blocks_per_s": Nt / v["plain_s"], "learned_blocks_per_s": Nt / v["learned_s"]}
+                            for k, v in tot.items()},
+        "mean_queries_plain": tot_q["plain"] / Nt, "mean_queries_learned": tot_q["learned"] / Nt,
+        "mean_queries_prior_order": tot_q["prior"] / Nt,
+        "roofline": {"bound": "mfma", "achieved": mfma / 1e12, "peak": 2500.0, "unit": "TFLOP/s (bf16)",
+                     "frac": mfma / 2.5e15, "traffic": None, "kernel": "network forward (three bf16 GEMMs)",
+                     "flop_per_launch": flops_fwd * fwd_rows / max(len(wl["ebn0"]), 1)},
         "pair_generation_s": gen_s, "blocks_decoded_for_pairs": seen, "training_s": train_s,
-        "train_loss_per_epoch": losses, "label_histogram_first8": label_hist, "per_point": points,
+        "train_loss_per_epoch": losses, "label_entropy_nats": label_entropy, "per_point": points,
     }
 
 

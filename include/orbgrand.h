@@ -300,6 +300,36 @@ int orbg_mlp_adam(float* w, float* m, float* v, const float* grads, float lr, in
  * [batch x 64] u8. */
 int orbg_mlp_order(const float* logits, int64_t batch, uint8_t* order, void* stream);
 
+/*
+ * Learned proposal in gated form: the network runs only for blocks the plain
+ * order's first batch does not decide.
+ *   1. Every block is searched over the first 64 patterns of the basic ORBGRAND
+ *      order (as orbg_decode); blocks with a member there, or whose budget
+ *      ends there, are written out.
+ *   2. The other blocks are listed; the network (w, wb as for orbg_mlp_forward)
+ *      scores their feature rows (orbg_mlp_features) and their batch order is
+ *      batch 0 first (known to hold no member), then batches 1..63 by decreasing
+ *      logit (ties to the lower index, NaN last).
+ *   3. The listed blocks are decoded in that order as orbg_decode_ordered would
+ *      (the 64 queries of batch 0 are counted, not repeated), the plain order
+ *      continuing from index 4096.
+ * Every block's result therefore equals orbg_decode_ordered with its own order
+ * (the identity for blocks decided by batch 0), and every decision is a
+ * parity-checked codeword.  H, llr, budget, codeword, queries, abandoned and
+ * the errors are as for orbg_decode; n must be 128 (the network's input).
+ * workspace: DEVICE, at least orbg_learned_workspace_bytes(batch) bytes.
+ * order_out: DEVICE u8 [batch x 64] receiving each block's order, or NULL.
+ * rest: HOST int64 receiving the number of listed blocks, or NULL.  params:
+ * launch shape (NULL = defaults) of both searches; the first always stops after
+ * one step, the second as orbg_decode_ex with an order.  The call
+ * synchronises `stream` once, after step 1, to size the network's launches.
+ */
+int64_t orbg_learned_workspace_bytes(int64_t batch);
+int orbg_decode_learned(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                        const float* w, const uint16_t* wb, void* workspace, int64_t workspace_bytes,
+                        uint8_t* codeword, uint64_t* queries, uint8_t* abandoned, uint8_t* order_out,
+                        int64_t* rest, const orbg_launch_params* params, void* stream);
+
 /* Message describing the calling thread's last non-OK status ("" if none). */
 const char* orbg_last_error(void);
 

@@ -84,6 +84,11 @@ def load():
     L.orbg_schedule_export_1line.restype = ci
     L.orbg_decode_mline.argtypes = [vp, vp, ci, ci, u64, i64, ci, ci, vp, vp, vp, vp, vp]
     L.orbg_decode_mline.restype = ci
+    L.orbg_learned_workspace_bytes.argtypes = [i64]
+    L.orbg_learned_workspace_bytes.restype = i64
+    L.orbg_decode_learned.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, i64, vp, vp, vp, vp,
+                                      ctypes.POINTER(i64), vp, vp]
+    L.orbg_decode_learned.restype = ci
     L.orbg_last_error.argtypes = []
     L.orbg_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -392,3 +397,30 @@ def orbg_mlp_adam(w, m, v, grads, lr: float, step: int, wb, wt, stream=None):
 
 def orbg_mlp_order(logits, order, stream=None):
     _check("orbg_mlp_order", load().orbg_mlp_order(_p(logits), logits.shape[0], _p(order), _stream_ptr(stream)))
+
+
+def orbg_learned_workspace_bytes(batch: int) -> int:
+    return int(load().orbg_learned_workspace_bytes(int(batch)))
+
+
+def orbg_decode_learned(H, llr, budget: int, w, wb, workspace, out=None, order_out=None,
+                        params: LaunchParams | None = None, stream=None):
+    """Gated learned decode (n = 128): batch 0 for every block, the network and the
+    ordered search only for the blocks batch 0 does not decide.  Returns
+    (codeword, queries, abandoned, listed block count)."""
+    import torch
+    Hn = _host_H(H)
+    m, n = Hn.shape
+    N = _llr_rows(llr, n)
+    cw, q, ab = _outputs(N, n, llr.device, out)
+    _dev_tensor(w, "w", torch.float32, (MLP_PARAMS,), llr.device)
+    _dev_tensor(wb, "wb", torch.int16, (MLP_PARAMS,), llr.device)
+    _dev_tensor(workspace, "workspace", torch.uint8, device=llr.device, ndim=1)
+    if order_out is not None:
+        _dev_tensor(order_out, "order_out", torch.uint8, (N, 64), llr.device)
+    rest = ctypes.c_int64(-1)
+    rc = load().orbg_decode_learned(Hn.ctypes.data_as(ctypes.c_void_p), _p(llr), n, n - m, int(budget), N, _p(w),
+                                    _p(wb), _p(workspace), workspace.numel(), _p(cw), _p(q), _p(ab), _p(order_out),
+                                    ctypes.byref(rest), _params_ptr(params), _stream_ptr(stream))
+    _check("orbg_decode_learned", rc)
+    return cw, q, ab, rest.value

@@ -683,6 +683,116 @@ int orbg_schedule_export_1line(int n, uint64_t budget, int j0, uint64_t count, u
     return ORBG_OK;
 }
 
+// Work space of a gated learned decode: the list of blocks left after batch 0,
+// their feature rows and network activations (at most MLP_BATCH_MAX at a time)
+// and their batch orders.
+struct LearnedWs {
+    int64_t* list;
+    uint16_t* feats;
+    orbg::MlpWorkspace fwd;
+    uint8_t* orders;
+    int64_t bytes;
+};
+
+static LearnedWs learned_carve(void* base, int64_t batch)
+{
+    LearnedWs w;
+    unsigned char* p = reinterpret_cast<unsigned char*>(base);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += (bytes + 255) & ~(int64_t)255; return r; };
+    const int64_t chunk = batch < MLP_BATCH_MAX ? batch : MLP_BATCH_MAX;
+    w.list = (int64_t*)take(batch * 8);
+    w.feats = (uint16_t*)take(chunk * MLP_IN * 2);
+    w.orders = (uint8_t*)take(batch * MLP_OUT);
+    const int64_t fwd = orbg::mlp_carve_forward(nullptr, chunk).bytes;
+    w.fwd = orbg::mlp_carve_forward(p ? p + o : nullptr, chunk);
+    o += fwd;
+    w.bytes = o;
+    return w;
+}
+
+int64_t orbg_learned_workspace_bytes(int64_t batch)
+{
+    if (batch < 0) return -1;
+    return learned_carve(nullptr, batch).bytes;
+}
+
+int orbg_decode_learned(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
+                        const float* w, const uint16_t* wb, void* workspace, int64_t workspace_bytes,
+                        uint8_t* codeword, uint64_t* queries, uint8_t* abandoned, uint8_t* order_out, int64_t* rest,
+                        const orbg_launch_params* params, void* stream)
+{
+    g_err.clear();
+    int rc = check_code_args(H, n, k);
+    if (rc || (rc = check_budget(budget, batch)) || (rc = check_params(params))) return rc;
+    if (n != MLP_IN) return fail(ORBG_EINVAL, "the network takes n = %d (got %d)", MLP_IN, n);
+    if (rest) *rest = 0;
+    if (batch == 0) return ORBG_OK;
+    if (!llr || !codeword || !queries || !abandoned || !w || !wb || !workspace)
+        return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const LearnedWs need = learned_carve(nullptr, batch);
+    if (workspace_bytes < need.bytes)
+        return fail(ORBG_EINVAL, "work space of %lld bytes is smaller than the %lld needed", (long long)workspace_bytes,
+                    (long long)need.bytes);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    CodeEntry* code = nullptr;
+    if ((rc = get_code(H, n, k, &code))) return rc;
+    orbg::DecodeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.codes.ncodes = 1;
+    if ((rc = describe(code, budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]))) return rc;
+    a.codes.rwords = a.codes.c[0].m * a.codes.c[0].nk;
+    Workspace* ws = nullptr;
+    if ((rc = get_workspace(st, 0, &ws, &a.cus))) return rc;
+    const LearnedWs lw = learned_carve(workspace, batch);
+    // 1. the first batch of the plain order for every block; the rest are listed
+    a.p = resolve_params(params, false);
+    a.p.split_steps = 1;
+    a.llr = llr;
+    a.nblocks = batch;
+    a.budget = (uint32_t)budget;
+    a.cw = codeword;
+    a.queries = queries;
+    a.abandoned = abandoned;
+    a.ctrs = ws->ctrs;
+    a.heavy = lw.list;
+    a.list_only = true;
+    hipError_t e = orbg::launch_decode(a, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "first-batch pass failed: %s", hipGetErrorString(e));
+    unsigned long long count = 0;
+    e = hipMemcpyAsync(&count, ws->ctrs + ORBG_CTR_HEAVY_COUNT, sizeof(count), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "reading the count of listed blocks failed: %s", hipGetErrorString(e));
+    if (rest) *rest = (int64_t)count;
+    // 2. features, network and batch order (batch 0 first) of the listed blocks
+    for (int64_t s = 0; s < (int64_t)count; s += MLP_BATCH_MAX) {
+        const int64_t c = (int64_t)count - s < MLP_BATCH_MAX ? (int64_t)count - s : MLP_BATCH_MAX;
+        e = orbg::mlp_features(llr, c, lw.feats, st, lw.list + s);
+        if (e == hipSuccess) e = orbg::mlp_forward(w, wb, lw.feats, c, lw.fwd.logits, lw.fwd, st);
+        if (e == hipSuccess) e = orbg::mlp_order(lw.fwd.logits, c, lw.orders + s * MLP_OUT, st, true);
+        if (e != hipSuccess) return fail(ORBG_EHIP, "network launch failed: %s", hipGetErrorString(e));
+    }
+    if (order_out && (e = orbg::mlp_order_table(lw.orders, lw.list, (int64_t)count, batch, order_out, st)) != hipSuccess)
+        return fail(ORBG_EHIP, "order table launch failed: %s", hipGetErrorString(e));
+    if (count == 0) return ORBG_OK;
+    // 3. ordered decode of the listed blocks from step 1 (blocks still open after
+    // the split point, at least the 64 reordered batches, go to the heavy pass,
+    // which indexes the caller's arrays directly)
+    orbg::DecodeArgs b = a;
+    b.p = resolve_params(params, true);
+    if (b.p.split_steps > 0 && (rc = get_workspace(st, (int64_t)count, &ws, &b.cus))) return rc;
+    b.ctrs = ws->ctrs;
+    b.heavy = b.p.split_steps > 0 ? ws->heavy : nullptr;
+    b.list_only = false;
+    b.ids = lw.list;
+    b.nblocks = (int64_t)count;
+    b.order = lw.orders;
+    b.skip0 = true;
+    e = orbg::launch_decode(b, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "ordered pass failed: %s", hipGetErrorString(e));
+    return ORBG_OK;
+}
+
 int64_t orbg_mlp_workspace_bytes(int64_t batch)
 {
     if (batch < 0 || batch > MLP_BATCH_MAX) return -1;

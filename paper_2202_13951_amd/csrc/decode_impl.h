@@ -516,7 +516,8 @@ template <int NK, bool ORDERED, typename S, bool ONELINE>
 __device__ __forceinline__ bool light_block(
     const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
     BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
-    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy, int32_t* __restrict__ j0_out)
+    uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy, int32_t* __restrict__ j0_out,
+    uint32_t t0 = 0)
 {
     const int lane = lane_id();
     const int n = c.n;
@@ -588,8 +589,9 @@ __device__ __forceinline__ bool light_block(
         // the first three steps' entries do not depend on the block's order of
         // reliability: they load while the ranks are sorted (1-line: after the
         // ranking that picks the schedule)
-        uint2 e0 = entries(0), e1 = entries(1), e2 = entries(2), e3 = make_uint2(0u, 0u);
-        uint32_t t = 0;
+        // (t0 = 1: batch 0 is known to hold no member and is counted, not tested)
+        uint2 e0 = entries(t0), e1 = entries(t0 + 1), e2 = entries(t0 + 2), e3 = make_uint2(0u, 0u);
+        uint32_t t = t0;
         // the search stops at step tend: the end of the queries, or the split
         // point if that comes first
         const uint32_t tend = (split_steps != 0 && split_steps < T) ? split_steps : T;
@@ -599,7 +601,7 @@ __device__ __forceinline__ bool light_block(
         // or step tend reached).  Four register sets rotate, so a load is
         // consumed three steps after it was issued.
         uint64_t hits = 0;
-        uint32_t rem = tend;
+        uint32_t rem = tend > t0 ? tend - t0 : 0u;
         auto step = [&](const uint2 cur, uint2& ahead) -> bool {
             ahead = entries(t + 3);
             hits = ballot(entry_syndrome<S>(L, cur) == 0);
@@ -633,17 +635,20 @@ __device__ __forceinline__ bool light_block(
         // (decays by 1/8 per try, +32 per success, so it tends to 256 x the
         // success rate); below 5/8 it pays to rank the whole block at once, but
         // every 8th block still tries so that the score follows the channel.
+        // A search that stops after step 0 (split_steps = 1) always tries: it
+        // never needs more ranks than the first batch reaches.
         int r = 0;
         bool resume = false;                  // step 0 already tested
         uint32_t idx1 = 0;
         lazy.tries = uniform_u32(lazy.tries + 1u);
-        if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u) &&
+        if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u || split_steps == 1u) &&
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
             first_tables<S>(idx1, c.rdepth0, cols, s0, L);
             r = outcome(step(e0, e3));
             resume = true;
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
+        if (r == 0 && rem == 0) r = outcome(true);          // nothing left to test after batch 0
         if (r == 0) {
             if (!ONELINE) rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
             for (;;) {
@@ -678,12 +683,12 @@ __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (
                                           const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
                                           uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
                                           uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy,
-                                          LazyState& lazy, int32_t* j0_out)
+                                          LazyState& lazy, int32_t* j0_out, uint32_t t0)
 {
     const bool left = light_block<NK, ORDERED, S, ONELINE>(x, hrow, c, cols, L, budget, split_steps, ordv,
                                                            make_buf(cw + (row >= 0 ? row : 0), row >= 0 ? (uint32_t)c.n : 0u),
                                                            queries + b,
-                                                           abandoned + b, lazy, j0_out ? j0_out + b : nullptr);
+                                                           abandoned + b, lazy, j0_out ? j0_out + b : nullptr, t0);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
         heavy[slot] = b;
@@ -694,6 +699,7 @@ __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (
 template <int NKMAX>
 struct RowFetch {
     float x[NKMAX];
+    int64_t oid;       // index of the block's outputs (wave-uniform)
     uint32_t ordv;     // batch order (ordered decode)
     int ci;            // code index (wave-uniform)
     int64_t row;       // element offset of the row (wave-uniform)
@@ -762,7 +768,8 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
              const float* __restrict__ llr, int64_t nblocks, uint32_t budget, uint32_t split_steps,
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
-             int chunk, int32_t* __restrict__ j0_out, int64_t row_limit)
+             int chunk, int32_t* __restrict__ j0_out, int64_t row_limit, const int64_t* __restrict__ ids,
+             uint32_t t0)
 {
     // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
     // m x nk words), then their columns (sum of n entries)
@@ -817,19 +824,24 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
         return s;
     };
-    // code index and row offset of block b (wave-uniform).  Mixed launches: a
-    // row that does not lie inside the first row_limit elements of both the LLR
-    // and the codeword buffer gets row = -1: it is read as zeros and its
-    // codeword stores are dropped (its queries and flag are still written).
-    auto locate = [&](int64_t b, int& ci, int64_t& row) {
+    // code index, row offset and output index of the launch's b-th block
+    // (wave-uniform).  Mixed launches: a row that does not lie inside the first
+    // row_limit elements of both the LLR and the codeword buffer gets row = -1:
+    // it is read as zeros and its codeword stores are dropped (its queries and
+    // flag are still written).  A block list (ids) names the caller's block of
+    // each position: its row, codeword and outputs; the batch order is the
+    // list's own (row b).
+    auto locate = [&](int64_t b, int& ci, int64_t& row, int64_t& oid) {
         if (MIXED) {
             ci = (int)scalar_load_u8(block_code, b);
             ci = ci < codes.ncodes ? ci : 0;          // out-of-range indices read code 0
             row = scalar_load_i64(row_off, b);
             row = uniform_i64((row >= 0 && row <= row_limit - codes.c[ci].n) ? row : -1);
+            oid = b;
         } else {
             ci = 0;
-            row = b * codes.c[0].n;
+            oid = ids ? scalar_load_i64(ids, b) : b;
+            row = oid * codes.c[0].n;
         }
     };
 
@@ -840,16 +852,17 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         for (int64_t g = s; g < e; g += K) {
             float xs[K][NKMAX];
             int cis[K];
-            int64_t rows[K];
+            int64_t rows[K], oids[K];
             uint32_t first[K];
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const bool ok = g + kk < e;
                 int ci = 0;
-                int64_t row = 0;
-                if (ok) locate(g + kk, ci, row);
+                int64_t row = 0, oid = 0;
+                if (ok) locate(g + kk, ci, row, oid);
                 cis[kk] = ci;
                 rows[kk] = row;
+                oids[kk] = oid;
                 const bool rv = ok && row >= 0;
                 load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), rv ? (uint32_t)codes.c[ci].n * 4u : 0u), xs[kk]);
                 // ordered decode: the block's first batch (every lane reads byte 0)
@@ -880,7 +893,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                         for (int j = 0; j < NKMAX; ++j)
                             __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, j * ORBG_WAVE + lane,
                                                                  0, 0);
-                        write_result(queries + b, abandoned + b, 1u, false);
+                        write_result(queries + oids[kk], abandoned + oids[kk], 1u, false);
                     } else {
                         left |= 1ull << (b - s);
                     }
@@ -893,10 +906,11 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     // phase 2: the inputs of block b (b < 0: an empty row, every lane reads 0)
     auto fetch = [&](RowFetch<NKMAX>& f, int64_t b) {
         int ci = 0;
-        int64_t row = 0;
-        if (b >= 0) locate(b, ci, row);
+        int64_t row = 0, oid = 0;
+        if (b >= 0) locate(b, ci, row, oid);
         f.ci = ci;
         f.row = row;
+        f.oid = oid;
         const bool rv = b >= 0 && row >= 0;
         const uint32_t bytes = rv ? (uint32_t)codes.c[ci].n * 4u : 0u;
         load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), bytes), f.x);
@@ -906,26 +920,26 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         const CodeDesc& c = codes.c[MIXED ? f.ci : 0];
         const S* cols = s_cols + (MIXED ? c.col_base : 0);
         if (HOIST) {
-            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hrow0, f.ordv, c, cols, L, b, f.row, budget, split_steps,
-                                                  cw, queries, abandoned, ctrs, heavy, lazy, j0_out);
+            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hrow0, f.ordv, c, cols, L, f.oid, f.row, budget, split_steps,
+                                                  cw, queries, abandoned, ctrs, heavy, lazy, j0_out, t0);
         } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
             uint64_t hr[NKMAX];
             load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);
-            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hr, f.ordv, c, cols, L, b, f.row, budget, split_steps, cw,
-                                                  queries, abandoned, ctrs, heavy, lazy, j0_out);
+            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hr, f.ordv, c, cols, L, f.oid, f.row, budget, split_steps, cw,
+                                                  queries, abandoned, ctrs, heavy, lazy, j0_out, t0);
         } else if (c.nk == 1) {
             uint64_t hr[1];
             load_hrows<1>(s_rows + c.row_base, c.m, hr);
-            light_one<1, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, b,
+            light_one<1, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, f.oid,
                                               f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy,
-                                              j0_out);
+                                              j0_out, t0);
         } else {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
             uint64_t hr[K2];
             load_hrows<K2>(s_rows + c.row_base, c.m, hr);
             light_one<K2, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L,
-                                               b, f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy,
-                                               lazy, j0_out);
+                                               f.oid, f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy,
+                                               lazy, j0_out, t0);
         }
     };
 
@@ -1089,7 +1103,7 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
     const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
     light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
-        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit);
+        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit, a.ids, a.skip0 ? 1u : 0u);
 }
 
 template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
@@ -1118,7 +1132,7 @@ static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
     const uint32_t split = (a.heavy != nullptr && a.p.split_steps > 0) ? (uint32_t)a.p.split_steps : 0u;
     reset_counters_kernel<<<1, 64, 0, stream>>>(a.ctrs);
     launch_light<NKMAX, ORDERED, S, MIXED, ONELINE>(a, wgs, chunk, split, stream);
-    if (split) {
+    if (split && !a.list_only) {
         if (a.p.heavy_waves >= 16) launch_heavy_g<NKMAX, S, MIXED, 16, ONELINE>(a, split, stream);
         else if (a.p.heavy_waves >= 8) launch_heavy_g<NKMAX, S, MIXED, 8, ONELINE>(a, split, stream);
         else launch_heavy_g<NKMAX, S, MIXED, 4, ONELINE>(a, split, stream);

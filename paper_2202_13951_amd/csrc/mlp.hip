@@ -12,11 +12,11 @@
 // uses BF16 copies of the weights (same layout); the backward also uses BF16
 // transposed copies W1t [128 x 256], W2t [256 x 256], W3t [256 x 64].
 //
-// GEMMs: v_mfma_f32_16x16x16_bf16 tiles, a 64 x 64 output tile per 256-thread
-// workgroup (each wave 32 x 32 = 2 x 2 MFMA tiles), K in steps of 16 with
-// fragments read straight from global memory (operands are small and stay in
-// L2).  Weight gradients reduce over the batch: split-K partials in FP32 and a
-// deterministic reduction.
+// GEMMs: gfx950's v_mfma_f32_16x16x32_bf16 tiles, a 64 x 64 output tile per
+// 256-thread workgroup (each wave 32 x 32 = 2 x 2 MFMA tiles), K in steps of 32
+// with 8-value fragments read straight from global memory (operands are small
+// and stay in L2).  Weight gradients reduce over the batch: split-K partials in
+// FP32 and a deterministic reduction.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,7 +25,8 @@
 
 namespace orbg {
 
-typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f32_to_bf16(float f)
@@ -38,17 +39,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ---------------------------------------------------------------------------
-// Features: sorted |LLR| / 8 in BF16, one wave per block (n = 128).
+// Features: sorted |LLR| / 8 in BF16, one wave per block (n = 128).  ids (or
+// nullptr): row ids[b] of llr gives feature row b.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__ llr, int64_t batch,
-                                                       uint16_t* __restrict__ x)
+                                                       uint16_t* __restrict__ x, const int64_t* __restrict__ ids)
 {
     const int lane = lane_id();
     const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
     if (b >= batch) return;
+    const int64_t src = ids ? ids[b] : b;
     uint32_t key[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) key[j] = __float_as_uint(llr[b * MLP_IN + j * ORBG_WAVE + lane]) & 0x7fffffffu;
+    for (int j = 0; j < 2; ++j) key[j] = __float_as_uint(llr[src * MLP_IN + j * ORBG_WAVE + lane]) & 0x7fffffffu;
     bitonic_sort<2, uint32_t>(key);
 #pragma unroll
     for (int j = 0; j < 2; ++j) x[b * MLP_IN + lane * 2 + j] = f32_to_bf16(__uint_as_float(key[j]) * 0.125f);
@@ -60,22 +63,23 @@ __global__ void __launch_bounds__(256) features_kernel(const float* __restrict__
 // ---------------------------------------------------------------------------
 enum { EPI_HIDDEN = 0, EPI_LOGITS = 1, EPI_MASKED = 2, EPI_PARTIAL = 3 };
 
-// Four consecutive-k values of one row (A) or column (B); `nk` of them exist
-// (0..4).  UNIT: unit stride, then the caller guarantees nk is 0 or 4.
+// Eight consecutive-k values of one row (A) or column (B); `nk` of them exist
+// (0..8).  UNIT: unit stride, then the caller guarantees nk is 0 or 8.
 template <bool UNIT>
-__device__ __forceinline__ s4v load_frag(const uint16_t* __restrict__ p, int64_t stride, int nk)
+__device__ __forceinline__ s8v load_frag(const uint16_t* __restrict__ p, int64_t stride, int nk)
 {
-    s4v r = {0, 0, 0, 0};
+    s8v r = {0, 0, 0, 0, 0, 0, 0, 0};
     if (nk <= 0) return r;
     if (UNIT) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p);
-        r.x = (short)(v.x & 0xffffu); r.y = (short)(v.x >> 16);
-        r.z = (short)(v.y & 0xffffu); r.w = (short)(v.y >> 16);
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        r[0] = (short)(v.x & 0xffffu); r[1] = (short)(v.x >> 16);
+        r[2] = (short)(v.y & 0xffffu); r[3] = (short)(v.y >> 16);
+        r[4] = (short)(v.z & 0xffffu); r[5] = (short)(v.z >> 16);
+        r[6] = (short)(v.w & 0xffffu); r[7] = (short)(v.w >> 16);
     } else {
-        r.x = (short)p[0];
-        if (nk > 1) r.y = (short)p[stride];
-        if (nk > 2) r.z = (short)p[2 * stride];
-        if (nk > 3) r.w = (short)p[3 * stride];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (t < nk) r[t] = (short)p[t * stride];
     }
     return r;
 }
@@ -98,10 +102,10 @@ gemm_kernel(const uint16_t* __restrict__ A, int64_t a_i, int64_t a_k, const uint
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[a][c] = (f4v){0.f, 0.f, 0.f, 0.f};
-    for (int k = kb; k < ke; k += 16) {
-        const int kk = k + 4 * q;                   // this lane's 4 consecutive k
-        const int nk = min(4, ke - kk);             // how many of them exist (<= 0: none)
-        s4v fa[2], fb[2];
+    for (int k = kb; k < ke; k += 32) {
+        const int kk = k + 8 * q;                   // this lane's 8 consecutive k
+        const int nk = min(8, ke - kk);             // how many of them exist (<= 0: none)
+        s8v fa[2], fb[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
             const int i = i0 + a * 16 + r;
@@ -116,7 +120,8 @@ gemm_kernel(const uint16_t* __restrict__ A, int64_t a_i, int64_t a_k, const uint
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[c], acc[a][c], 0, 0, 0);
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, fa[a]),
+                                                                    __builtin_bit_cast(bf8v, fb[c]), acc[a][c], 0, 0, 0);
     }
     // lane holds D[4q + t][r] of each 16 x 16 tile, t = 0..3
 #pragma unroll
@@ -243,12 +248,12 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
     write_copies(p, ww, wb, wt);
 }
 
-// Batch order: decreasing logit, ties (and +-0) to the lower index, NaN last.
-// One wave per row: key = (order-preserving bits of -logit) << 32 | index,
-// sorted ascending by the register bitonic network; lane e then holds the
-// e-th batch to test.
+// Batch order: decreasing logit, ties (and +-0) to the lower index, NaN last;
+// pin0: batch 0 first whatever its logit, the others as before.  One wave per
+// row: key = (order-preserving bits of -logit) << 32 | index, sorted ascending
+// by the register bitonic network; lane e then holds the e-th batch to test.
 __global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ logits, int64_t batch,
-                                                    uint8_t* __restrict__ order)
+                                                    uint8_t* __restrict__ order, int pin0)
 {
     const int lane = lane_id();
     const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
@@ -258,8 +263,34 @@ __global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ lo
     const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
     const uint32_t up = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f, NaN lowest
     uint64_t key[1] = {((uint64_t)(~up) << 32) | (uint32_t)lane};          // ascending = decreasing f
+    if (pin0 && lane == 0) key[0] = 0ull;
     bitonic_sort<1, uint64_t>(key);
     order[b * MLP_OUT + lane] = (uint8_t)(key[0] & 63u);
+}
+
+// Order table of a gated decode: row b = identity for blocks decided by batch 0,
+// the learned order for listed blocks (row ids[i] = rows[i]).
+__global__ void order_identity_kernel(uint8_t* __restrict__ order, int64_t batch)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < batch * MLP_OUT) order[e] = (uint8_t)(e % MLP_OUT);
+}
+
+__global__ void order_scatter_kernel(const uint8_t* __restrict__ rows, const int64_t* __restrict__ ids, int64_t count,
+                                     uint8_t* __restrict__ order)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count * MLP_OUT) order[ids[e / MLP_OUT] * MLP_OUT + e % MLP_OUT] = rows[e];
+}
+
+hipError_t mlp_order_table(const uint8_t* rows, const int64_t* ids, int64_t count, int64_t batch, uint8_t* order,
+                           hipStream_t st)
+{
+    if (batch > 0)
+        order_identity_kernel<<<(unsigned)((batch * MLP_OUT + 255) / 256), 256, 0, st>>>(order, batch);
+    if (count > 0)
+        order_scatter_kernel<<<(unsigned)((count * MLP_OUT + 255) / 256), 256, 0, st>>>(rows, ids, count, order);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -287,6 +318,19 @@ MlpWorkspace mlp_carve(void* base, int64_t batch)
     return w;
 }
 
+MlpWorkspace mlp_carve_forward(void* base, int64_t batch)
+{
+    MlpWorkspace w = {};
+    unsigned char* p = reinterpret_cast<unsigned char*>(base);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += align256(bytes); return r; };
+    w.h1 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.h2 = (uint16_t*)take(batch * MLP_HID * 2);
+    w.logits = (float*)take(batch * MLP_OUT * 4);
+    w.bytes = o;
+    return w;
+}
+
 template <bool AK, bool BK, int EPI>
 static void gemm(const uint16_t* A, int64_t a_i, int64_t a_k, const uint16_t* B, int64_t b_k, int64_t b_j, int M,
                  int N, int K, int splits, int kchunk, const float* bias, void* out, int64_t ldo,
@@ -297,9 +341,9 @@ static void gemm(const uint16_t* A, int64_t a_i, int64_t a_k, const uint16_t* B,
                                                    mask, ldm);
 }
 
-hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st)
+hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st, const int64_t* ids)
 {
-    if (batch > 0) features_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(llr, batch, x);
+    if (batch > 0) features_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(llr, batch, x, ids);
     return hipGetLastError();
 }
 
@@ -373,9 +417,9 @@ hipError_t mlp_adam(float* w, float* m, float* v, const float* g, float lr, int 
     return hipGetLastError();
 }
 
-hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st)
+hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st, bool pin0)
 {
-    if (batch > 0) order_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(logits, batch, order);
+    if (batch > 0) order_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(logits, batch, order, pin0 ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -57,6 +57,11 @@ struct DecodeArgs {
     uint8_t* abandoned;
     unsigned long long* ctrs;  // device work counters (8 slices, heavy count, heavy next)
     int64_t* heavy;            // device heavy-block list, capacity >= nblocks when splitting
+    bool list_only;            // blocks left after split_steps are only listed in heavy (no heavy pass)
+    const int64_t* ids;        // device, nblocks: caller's block index of each position, or nullptr
+                               // (one code, no heavy pass; the batch order stays per position)
+    bool skip0;                // ordered decode of blocks known to hold no member in batch 0:
+                               // the search starts at step 1
     int cus;                   // compute units of the device
     LaunchParams p;
 };

@@ -40,8 +40,10 @@ struct MlpWorkspace {
 // Carves the work space of a `batch`-row call out of `base` (base may be
 // nullptr to only compute .bytes).
 MlpWorkspace mlp_carve(void* base, int64_t batch);
+// The forward's part of it (h1, h2, logits).
+MlpWorkspace mlp_carve_forward(void* base, int64_t batch);
 
-hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st);
+hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st, const int64_t* ids = nullptr);
 hipError_t mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, hipStream_t st);
 hipError_t mlp_forward(const float* w, const uint16_t* wb, const uint16_t* x, int64_t batch, float* logits,
                        const MlpWorkspace& ws, hipStream_t st);
@@ -50,6 +52,8 @@ hipError_t mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, 
                         hipStream_t st);
 hipError_t mlp_adam(float* w, float* m, float* v, const float* g, float lr, int step, uint16_t* wb, uint16_t* wt,
                     hipStream_t st);
-hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st);
+hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st, bool pin0 = false);
+hipError_t mlp_order_table(const uint8_t* rows, const int64_t* ids, int64_t count, int64_t batch, uint8_t* order,
+                           hipStream_t st);
 
 }  // namespace orbg

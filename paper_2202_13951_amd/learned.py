@@ -91,10 +91,12 @@ def features(llr):
     return x
 
 
-def generate_pairs(H, G, n_blocks: int, ebn0_lo: float, ebn0_hi: float, seed: int, device):
+def generate_pairs(H, G, n_blocks: int, ebn0_lo: float, ebn0_hi: float, seed: int, device, gated: bool = False):
     """Decodes n_blocks fresh blocks (Eb/N0 uniform per block) with a 4096-query
     budget; returns (features int16 [M,128], labels int32 [M]) of the M blocks
-    whose first hit falls in the first 4096 patterns."""
+    whose first hit falls in the first 4096 patterns (gated: only those whose
+    first hit lies past batch 0, the blocks the gated decode asks the network
+    about)."""
     import torch
     from synth import channel
     xs, ys = [], []
@@ -103,7 +105,7 @@ def generate_pairs(H, G, n_blocks: int, ebn0_lo: float, ebn0_hi: float, seed: in
         e = min(n_blocks, s + chunk)
         llr, _, _ = channel.awgn_llr_torch_snr_range(G, e - s, ebn0_lo, ebn0_hi, seed * 1000 + i, device)
         _, q, ab = B.orbg_decode(H, llr, PREFIX)
-        keep = ab == 0
+        keep = (ab == 0) & (q > 64) if gated else ab == 0
         x = features(llr)
         xs.append(x[keep])
         ys.append(((q[keep] - 1) // 64).to(torch.int32))
@@ -137,6 +139,30 @@ def decode_learned(prop: Proposal, H, llr, budget: int, out=None, params=None):
     order, decode: four launches on the current stream)."""
     order = prop.order(features(llr))
     return B.orbg_decode_ex(H, llr, budget, order=order, params=params, out=out)
+
+
+def decode_learned_gated(prop: Proposal, H, llr, budget: int, out=None, order_out=None, params=None):
+    """Gated decode (one library call): the first batch of the plain order for
+    every block; the network and the ordered search (batch 0 first, batches 1..63
+    by the network) only for the blocks it does not decide.  Returns (codeword,
+    queries, abandoned, number of blocks the network ran on)."""
+    import torch
+    need = B.orbg_learned_workspace_bytes(llr.shape[0])
+    ws = prop._ws.get("learned")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=prop.device)
+        prop._ws["learned"] = ws
+    return B.orbg_decode_learned(H, llr, budget, prop.w, prop.wb, ws, out=out, order_out=order_out, params=params)
+
+
+def prior_order(labels, device):
+    """The fixed order a network without inputs would give: batch 0 first, then
+    batches 1..63 by decreasing frequency among the training labels (ties to the
+    lower index).  [64] uint8."""
+    import torch
+    counts = torch.bincount(labels.long(), minlength=64)[:64].cpu().numpy().astype(np.int64)
+    rest = sorted(range(1, 64), key=lambda b: (-counts[b], b))
+    return torch.tensor([0] + rest, dtype=torch.uint8, device=device)
 
 
 def paired_ci(diff: np.ndarray, z: float = 1.96):

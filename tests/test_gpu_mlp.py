@@ -4,7 +4,9 @@ trained network gains over plain ORBGRAND.
 Tolerances: features and the batch order are compared bit for bit (same
 rounding, same comparison rule).  Logits: BF16 activations are rounded at the
 same points on both sides, but FP32 accumulation in a different order can move
-an activation across a BF16 rounding boundary, so |gpu - ref| <= 2e-2 (1 + |ref|).
+an activation across a BF16 rounding boundary (one BF16 step, 2^-8 relative),
+so each row's logits must agree in the max norm to 1e-2 of the row's largest
+|logit| (measured: below 1e-6 for 100 rows, 8e-4 for 2500, 2.6e-3 for 20000).
 Gradients: the GPU also rounds the backward's GEMM inputs to BF16 (relative
 error 2^-9 per value), so each parameter tensor must reach cosine >= 0.999 and
 a relative norm error <= 3e-2; the loss matches to 1e-3 relative.
@@ -58,7 +60,8 @@ def test_forward_matches_reference(gpu_device, N):
     x = learned.features(torch.from_numpy(llr).to(gpu_device))
     lg = p.logits(x).cpu().numpy()
     ref, _ = M.forward(w, _bits_to_f32(x))
-    assert (np.abs(lg - ref) <= 2e-2 * (1 + np.abs(ref))).all()
+    rowmax = np.abs(ref).max(axis=1, keepdims=True)
+    assert (np.abs(lg - ref) <= 1e-2 * rowmax).all(), float((np.abs(lg - ref) / rowmax).max())
     # the BF16 copies are the reference rounding of the masters
     assert (p.wb.cpu().numpy().view(np.uint16) == M.bf16_bits(w)).all()
     wt = p.wt.cpu().numpy().view(np.uint16)
@@ -124,34 +127,81 @@ def test_order_bit_exact(gpu_device):
     assert (order.cpu().numpy() == M.order(lg)).all()
 
 
-def test_trained_proposal_gains_over_plain(gpu_device):
-    """Train on pairs the decoder generates (RLC(128,105), Eb/N0 ~ U[3,5] dB), then
-    on held-out blocks at 4 dB: mean queries drop (paired 95% interval below 0),
-    block errors stay within their 95% interval, and the ordered decode with the
-    learned order equals the oracle's ordered decode bit for bit on a sample."""
+def test_trained_proposal_gains_over_plain_and_prior(gpu_device):
+    """Train on the pairs the gated decode asks about (RLC(128,105), Eb/N0 ~
+    U[3,5] dB, blocks whose first hit lies in batches 1..63); the final training
+    loss ends below the entropy of the labels (what predicting the label
+    frequencies alone gives).  On held-out blocks at 4 dB the gated decode needs
+    fewer queries than plain ORBGRAND and than the fixed prior order (batch 0,
+    then batches by training-label frequency), both paired 95% intervals below
+    0, and its block errors stay within their 95% interval of plain's."""
     print("train proposal", flush=True)
     H, G = codes.code("rlc128_105")
-    x, y = learned.generate_pairs(H, G, 600000, 3.0, 5.0, seed=1, device=gpu_device)
-    assert x.shape[0] > 300000
+    x, y = learned.generate_pairs(H, G, 3000000, 3.0, 5.0, seed=1, device=gpu_device, gated=True)
+    assert x.shape[0] > 600000 and int(y.min()) >= 1
+    hist = torch.bincount(y.long(), minlength=64).cpu().numpy().astype(np.float64)
+    p = hist[hist > 0] / hist.sum()
+    entropy = float(-(p * np.log(p)).sum())
     prop = learned.Proposal(gpu_device, seed=0)
-    losses = learned.train(prop, x, y, epochs=3, batch=8192, lr=2e-3)
-    assert losses[-1] < 0.8 * np.log(64), losses
-    print(f"losses {losses}", flush=True)
-    llr, sent = channel.awgn_llr_torch(G, 40000, 4.0, seed=777, device=gpu_device)
+    losses = learned.train(prop, x, y, epochs=4, batch=8192, lr=2e-3)
+    print(f"losses {losses}, label entropy {entropy:.4f}", flush=True)
+    assert losses[-1] < entropy, (losses, entropy)
+    prior = learned.prior_order(y, gpu_device)
+    llr, sent = channel.awgn_llr_torch(G, 200000, 4.0, seed=777, device=gpu_device)
     budget = 10 ** 5
     pc, pq, pab = binding.orbg_decode(H, llr, budget)
-    lc, lq, lab = learned.decode_learned(prop, H, llr, budget)
+    lc, lq, lab, rest = learned.decode_learned_gated(prop, H, llr, budget)
+    rc, rq, rab = binding.orbg_decode_ordered(H, llr, budget, prior.unsqueeze(0).expand(llr.shape[0], 64).contiguous())
     torch.cuda.synchronize()
-    pq, lq = pq.cpu().numpy().astype(np.float64), lq.cpu().numpy().astype(np.float64)
-    mu, (lo, hi) = learned.paired_ci(lq - pq)
-    print(f"mean queries plain {pq.mean():.2f} learned {lq.mean():.2f} diff {mu:.2f} [{lo:.2f}, {hi:.2f}]",
-          flush=True)
-    assert hi < 0
+    pqn, lqn, rqn = (t.cpu().numpy().astype(np.float64) for t in (pq, lq, rq))
+    mu, (lo, hi) = learned.paired_ci(lqn - pqn)
+    mur, (lor, hir) = learned.paired_ci(lqn - rqn)
+    print(f"network ran on {rest} blocks; mean queries plain {pqn.mean():.2f} learned {lqn.mean():.2f} "
+          f"prior {rqn.mean():.2f}; learned - plain {mu:.2f} [{lo:.2f}, {hi:.2f}], "
+          f"learned - prior {mur:.2f} [{lor:.2f}, {hir:.2f}]", flush=True)
+    assert hi < 0 and hir < 0
     pe = int((pc != sent).any(dim=1).sum())
     le = int((lc != sent).any(dim=1).sum())
     assert abs(le - pe) <= 1.96 * np.sqrt(pe + le) + 2, (pe, le)
-    # bit-exact against the oracle's ordered decode on a sample, with the GPU's order
-    order = prop.order(learned.features(llr))
-    idx = np.arange(0, 40000, 100)
-    oc, oq, oab = O.decode_ordered(H, llr.cpu().numpy()[idx], budget, order.cpu().numpy()[idx], THREADS)
-    assert (lc.cpu().numpy()[idx] == oc).all() and (lq[idx].astype(np.uint64) == oq).all()
+
+
+def _listed_case(dev, N=6000, ebn0=3.5, seed=4242):
+    H, G = codes.code("rlc128_105")
+    llr, sent = channel.awgn_llr_torch(G, N, ebn0, seed=seed, device=dev)
+    return H, G, llr, sent
+
+
+@pytest.mark.parametrize("budget", [64, 3000, 10 ** 5])
+def test_gated_decode_matches_oracle(gpu_device, budget):
+    """The gated decode (batch 0 for every block, the network and the ordered
+    search for the rest) against the oracle's ordered decode with the order each
+    block was given: every block's codeword, queries and flag, bit for bit; the
+    blocks the network ran on are exactly those plain ORBGRAND does not decide in
+    its first 64 queries, their orders start with batch 0 and rank the others by
+    the network's logits; every other block keeps the identity order."""
+    print(f"gated decode, budget {budget}", flush=True)
+    H, G, llr, sent = _listed_case(gpu_device)
+    N = llr.shape[0]
+    prop = learned.Proposal(gpu_device, seed=3)          # an untrained network gives some order
+    order = torch.empty((N, 64), dtype=torch.uint8, device=gpu_device)
+    cw, q, ab, rest = learned.decode_learned_gated(prop, H, llr, budget, order_out=order)
+    pc, pq, pab = binding.orbg_decode(H, llr, budget)
+    torch.cuda.synchronize()
+    llr_np, order_np = llr.cpu().numpy(), order.cpu().numpy()
+    pqn = pq.cpu().numpy()
+    listed = pqn > 64
+    assert rest == int(listed.sum())
+    assert rest > (0 if budget > 64 else -1)
+    ident = np.arange(64, dtype=np.uint8)
+    assert (order_np[~listed] == ident).all()
+    oc, oq, oab = O.decode_ordered(H, llr_np, budget, order_np, THREADS)
+    assert (cw.cpu().numpy() == oc).all()
+    assert (q.cpu().numpy().astype(np.uint64) == oq).all()
+    assert (ab.cpu().numpy() == oab).all()
+    if rest:
+        idx = np.nonzero(listed)[0]
+        rows = torch.from_numpy(idx).to(gpu_device)
+        x = learned.features(llr[rows].contiguous())
+        lg = prop.logits(x).cpu().numpy()
+        want = M.order(np.concatenate([np.full((len(idx), 1), np.inf), lg[:, 1:]], axis=1))
+        assert (order_np[idx] == want).all()
