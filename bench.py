@@ -183,7 +183,7 @@ def kernel_fingerprint(sources=DECODE_SOURCES) -> str:
 def profiled_traffic(workload: str, prefix: str = "decode_kernel", sources=DECODE_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary of
     this workload, or None if there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"{prefix}_{WORKLOADS[workload]['code']}.md")
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{WORKLOADS[workload].get('code', workload)}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -220,9 +220,16 @@ def cpu_baseline(H, rows, npoints: int, per_max: int, budget, target_s=20.0, one
         dec(H, x, budget, threads)
     dt = time.perf_counter() - t0
     nb = per * npoints
-    return {"value": nb / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle",
+    # the same oracle on one core, on a sample sized to about a quarter of target_s
+    per1 = max(1, int(per * (target_s / 4) / max(dt * threads, 1e-3)))
+    t0 = time.perf_counter()
+    for p in range(npoints):
+        dec(H, xs[p][:per1], budget, 1)
+    dt1 = time.perf_counter() - t0
+    return {"value": nb / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "one_core_value": per1 * npoints / dt1,
             "sample": f"first {per} blocks of each of the {npoints} Eb/N0 points "
-                      f"({nb} blocks, {dt:.1f} s wall)"}
+                      f"({nb} blocks, {dt:.1f} s wall); one core: first {per1} of each ({dt1:.1f} s)"}
 
 
 def single_inputs(wl, dev, points=None):
@@ -353,7 +360,7 @@ def run_single(args, wl, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": ("u32" if n - wl["k"] <= 32 else "u64") + " syndromes, FP32 LLR",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "code": wl["code"], "n": n, "k": wl["k"], "ebn0_db": wl["ebn0"],
                    "blocks_per_step": blocks, "budget": budget},
@@ -478,7 +485,7 @@ def run_oneline(args, wl, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": ("u32" if n - wl["k"] <= 32 else "u64") + " syndromes, FP32 LLR",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "code": wl["code"], "n": n, "k": wl["k"], "ebn0_db": wl["ebn0"],
                    "blocks_per_step": blocks, "budget": budget, "j0max": j0max},
@@ -501,14 +508,22 @@ def run_oneline(args, wl, dev):
 
 
 def run_mixed(args, wl, dev):
-    """Per Eb/N0 point: the tuned persistent mixed launch, and one launch per code
-    without the heavy pass, on the same blocks (results compared bit for bit)."""
+    """Per Eb/N0 point: the tuned persistent mixed launch against two baselines on
+    the same resident buffer, one launch per code over that code's blocks (a
+    one-code mixed call with the code's block list, reading the rows in place):
+    (a) the naive launch -- one one-wave workgroup per block, no work counter, no
+    heavy pass; (b) the persistent light pass without the heavy pass.  Results
+    are compared bit for bit."""
     import torch
     from paper_2202_13951_amd import binding
     params, knobs = tuned_params(args.workload, not args.no_tuned)
-    naive = binding.LaunchParams(split_steps=0)
+    shapes = {"one_block_per_workgroup": binding.LaunchParams(one_block_per_workgroup=1),
+              "persistent_per_code": binding.LaunchParams(split_steps=0)}
     stream = torch.cuda.current_stream()
-    points, tot_blocks, tot_ms, tot_naive_ms, tot_q = {}, 0, 0.0, 0.0, 0
+    points, tot_blocks, tot_ms, tot_q = {}, 0, 0.0, 0
+    tot_base = {k: 0.0 for k in shapes}
+    ops_tot, bytes_tot = 0.0, 0.0
+    cpu_rows = []                                     # (H, rows) of a bounded sample per point, for the oracle
 
     def timed(fn):
         return time_calls(fn, stream)
@@ -527,53 +542,109 @@ def run_mixed(args, wl, dev):
             mixed_fn()
         ms = [timed(mixed_fn) for _ in range(args.steps)]
         print(f"mixed {e} dB: {np.median(ms):.2f} ms", file=sys.stderr, flush=True)
-        # naive: per-code row-major copies, one launch each, no heavy pass
         per_code = []
         for ci, (H, G) in enumerate(HG):
             n = H.shape[1]
             idx = torch.nonzero(bc == ci).flatten()
-            rows = llr[(ro[idx][:, None] + torch.arange(n, device=dev)[None, :])].contiguous()
-            per_code.append((H, idx, rows, n))
-        outs = [(torch.empty(r.shape, dtype=torch.uint8, device=dev),
-                 torch.empty(r.shape[0], dtype=torch.int64, device=dev),
-                 torch.empty(r.shape[0], dtype=torch.uint8, device=dev)) for _, _, r, _ in per_code]
+            per_code.append((H, ids[ci], idx, torch.zeros(idx.numel(), dtype=torch.uint8, device=dev),
+                             ro[idx].contiguous(), n))
+        base_ms, same = {}, True
+        for name, P in shapes.items():
+            cwb = torch.empty_like(cw)
+            outs = [(torch.empty(idx.numel(), dtype=torch.int64, device=dev),
+                     torch.empty(idx.numel(), dtype=torch.uint8, device=dev)) for _, _, idx, _, _, _ in per_code]
 
-        def naive_fn():
-            for (H, idx, rows, n), o in zip(per_code, outs):
-                binding.orbg_decode_ex(H, rows, wl["budget"], params=naive, out=o)
-        naive_fn()
-        nms = [timed(naive_fn) for _ in range(args.steps)]
-        print(f"naive {e} dB: {np.median(nms):.2f} ms", file=sys.stderr, flush=True)
-        same = True
+            def base_fn():
+                for (H, cid, idx, zc, rc, n), o in zip(per_code, outs):
+                    binding.orbg_decode_mixed([cid], zc, rc, llr, wl["budget"], cwb, o[0], o[1], params=P)
+            base_fn()
+            base_ms[name] = float(np.median([timed(base_fn) for _ in range(args.steps)]))
+            print(f"{name} {e} dB: {base_ms[name]:.2f} ms", file=sys.stderr, flush=True)
+            for (H, cid, idx, zc, rc, n), o in zip(per_code, outs):
+                same &= bool((q[idx] == o[0]).all()) and bool((ab[idx] == o[1]).all())
+            same &= bool((cwb == cw).all())
+            del outs, cwb
         errs = torch.zeros(N, dtype=torch.bool, device=dev)
-        for (H, idx, rows, n), o in zip(per_code, outs):
-            pos = ro[idx][:, None] + torch.arange(n, device=dev)[None, :]
-            same &= bool((q[idx] == o[1]).all()) and bool((ab[idx] == o[2]).all())
-            same &= bool((cw[pos] == o[0]).all())
+        ops = 0.0
+        for H, cid, idx, zc, rc, n in per_code:
+            pos = rc[:, None] + torch.arange(n, device=dev)[None, :]
             errs[idx] = (cw[pos] != sent[pos]).any(dim=1)
+            qc = q[idx]
+            ops += algorithmic_ops(int(qc.sum()), int((qc > 1).sum()), n)
+            bytes_tot += idx.numel() * (5 * n + 9)
+            cpu_rows.append((H, llr[pos[:20000]].cpu().numpy()))
+        ops_tot += ops
         ne = int(errs.sum())
         qs = int(q.sum())
-        m, nm = float(np.median(ms)), float(np.median(nms))
-        points[f"{e:.1f}"] = {"blocks_per_s": N / (m / 1e3), "naive_blocks_per_s": N / (nm / 1e3),
-                              "speedup_vs_naive": nm / m, "ms": m, "naive_ms": nm, "mean_queries": qs / N,
+        m = float(np.median(ms))
+        points[f"{e:.1f}"] = {"blocks_per_s": N / (m / 1e3), "ms": m, "mean_queries": qs / N,
+                              "baselines_ms": base_ms,
+                              "baselines_blocks_per_s": {k: N / (v / 1e3) for k, v in base_ms.items()},
+                              "speedup": {k: v / m for k, v in base_ms.items()},
                               "bler": ne / N, "bler_ci95": list(wilson(ne, N)), "abandoned": int(ab.sum()),
-                              "identical_to_naive": same}
+                              "identical_to_baselines": same}
         tot_blocks += N
         tot_ms += m
-        tot_naive_ms += nm
+        for k in shapes:
+            tot_base[k] += base_ms[k]
         tot_q += qs
-        del HG, llr, sent, bc, ro, cw, q, ab, per_code, outs
+        del HG, llr, sent, bc, ro, cw, q, ab, per_code
         torch.cuda.empty_cache()
-    return {
-        "metric": METRIC, "value": tot_blocks / (tot_ms / 1e3), "unit": "blocks/s", "n_gpus": 1,
+    ksec = tot_ms / 1e3
+    result = {
+        "metric": METRIC, "value": tot_blocks / ksec, "unit": "blocks/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": tot_ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 syndromes, FP32 LLR", "data": "synthetic",
         "config": {"workload": wl["desc"], "codes": wl["codes"], "ratio": wl["ratio"], "ebn0_db": wl["ebn0"],
                    "blocks_per_point": wl["blocks"], "budget": wl["budget"]},
-        "queries_per_s": tot_q / (tot_ms / 1e3), "naive_value": tot_blocks / (tot_naive_ms / 1e3),
-        "speedup_vs_naive": tot_naive_ms / tot_ms, "launch_params": knobs if knobs else "library defaults",
+        "queries_per_s": tot_q / ksec,
+        "baselines_value": {k: tot_blocks / (v / 1e3) for k, v in tot_base.items()},
+        "speedup": {k: v / tot_ms for k, v in tot_base.items()},
+        "launch_params": knobs if knobs else "library defaults",
+        "roofline": {"bound": "alu", "achieved": ops_tot / ksec / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                     "unit": "Tops/s (int32)", "frac": ops_tot / ksec / PEAK_INT32_OPS,
+                     "traffic": profiled_traffic(args.workload) if not args.ebn0 else None,
+                     "kernel": "light_kernel<4> + heavy_kernel (one mixed decode call per point)",
+                     "ops_per_launch": ops_tot / len(wl["ebn0"]),
+                     "hbm": {"achieved_GBps": bytes_tot / ksec / 1e9, "peak_GBps": PEAK_HBM / 1e9,
+                             "frac": bytes_tot / ksec / PEAK_HBM, "bytes_per_launch": bytes_tot / len(wl["ebn0"])}},
         "per_point": points,
     }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_mixed(cpu_rows, wl["budget"], len(wl["ebn0"]))
+    return result
+
+
+def cpu_baseline_mixed(samples, budget, npoints, target_s=15.0):
+    """The oracle on the first blocks of every code at every point (each code's
+    blocks in launch order), sized to about target_s of work."""
+    from oracle import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    per = 20
+    t0 = time.perf_counter()
+    for H, x in samples:
+        O.decode(H, x[:per], budget, threads)
+    dt = time.perf_counter() - t0
+    per = int(min(min(len(x) for _, x in samples), max(per, per * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    for H, x in samples:
+        O.decode(H, x[:per], budget, threads)
+    dt = time.perf_counter() - t0
+    nb = per * len(samples)
+    return {"value": nb / dt, "unit": "blocks/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"first {per} blocks of each code at each of the {npoints} Eb/N0 points "
+                      f"({nb} blocks, {dt:.1f} s wall)"}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_stream(args, wl, dev):
@@ -711,7 +782,7 @@ def run_stream(args, wl, dev):
     return {
         "metric": METRIC, "value": top["blocks_per_s"], "unit": "blocks/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": 1e3 * wl["seconds"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 syndromes, FP32 LLR", "data": "synthetic",
         "config": {"workload": wl["desc"], "codes": wl["codes"], "rates_per_s": wl["rates"],
                    "ebn0_db_range": list(wl["ebn0_range"]), "budget": wl["budget"],
                    "capacity": wl["capacity"], "max_batch": wl["max_batch"]},
@@ -957,7 +1028,7 @@ def run_mline(args, wl, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64",
+        "dtype": "u64 syndromes, FP32 LLR and fit",
         "data": "synthetic",
         "config": {"workload": wl["desc"] if segments == wl["segments"] else
                    wl["desc"].replace("a 2-line fit", f"a fit of at most {segments} lines"),

@@ -23,10 +23,13 @@
  *     queries made, the empty pattern counting as the first), abandoned (one
  *     byte per block: 1 if the budget ran out, then queries == budget and the
  *     codeword row is the hard decision).
- *   - budget: the largest number of queries per block, 1 <= budget <= 2^22
- *     (4,194,304).  The query schedule stops at logistic weight 99, so for
- *     short codes (n < 22) a budget close to 2^n that would need patterns of
- *     larger logistic weight is rejected with ORBG_EINVAL.
+ *   - budget: the largest number of queries per block, 1 <= budget <= 5 x 10^6
+ *     (the abandonment threshold of Sec. IV-A; the 1-line decode takes at most
+ *     2^22).  The query schedule holds every pattern of logistic weight <= 99
+ *     and those of weight 100 up to {9, ..., 16} (the only pattern flipping
+ *     eight ranks above 8): 5,150,463 patterns for n >= 100, at least 5 x 10^6
+ *     for n >= 64; a budget for a short code that would need patterns past
+ *     them is rejected with ORBG_EINVAL.
  *   - stream: a hipStream_t (NULL = the default stream).  Decodes are
  *     asynchronous on that stream.  The first call for a new H, or for a new
  *     (n, budget) query schedule, allocates device memory and synchronises the
@@ -65,6 +68,9 @@ typedef struct orbg_launch_params {
                                      an ordered decode moves values below 64 up to 64 */
     int heavy_waves;              /* 4, 8 or 16 (default 8) */
     int heavy_workgroups_per_cu;  /* heavy pass, 1..16 (default 2) */
+    int one_block_per_workgroup;  /* 1: the naive launch -- one one-wave workgroup per block, no work
+                                     counter, no chunks, no heavy pass (other fields ignored); 0: the
+                                     persistent launch described above */
 } orbg_launch_params;
 
 /*
@@ -233,7 +239,7 @@ int orbg_decode_mixed_noalloc(const int* codes, int ncodes, const uint8_t* block
  * schedule for length n into the HOST buffer `out` (count x 16 bytes): entry g
  * lists the 1-based reliability ranks flipped by query g + 1 in increasing
  * order, padded with zeros (Sec. III-B/C order as described for orbg_decode).
- * 1 <= count <= 2^22 and count <= 2^n.  Synchronises `stream`.
+ * 1 <= count <= 5 x 10^6 and count <= 2^n.  Synchronises `stream`.
  */
 int orbg_schedule_export(int n, uint64_t count, uint8_t* out, void* stream);
 

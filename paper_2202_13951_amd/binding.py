@@ -24,10 +24,13 @@ _lib = None
 class LaunchParams(ctypes.Structure):
     """orbg_launch_params: 0 fields take the library defaults (split_steps: -1)."""
     _fields_ = [("workgroups_per_cu", ctypes.c_int), ("chunk", ctypes.c_int), ("split_steps", ctypes.c_int),
-                ("heavy_waves", ctypes.c_int), ("heavy_workgroups_per_cu", ctypes.c_int)]
+                ("heavy_waves", ctypes.c_int), ("heavy_workgroups_per_cu", ctypes.c_int),
+                ("one_block_per_workgroup", ctypes.c_int)]
 
-    def __init__(self, workgroups_per_cu=0, chunk=0, split_steps=-1, heavy_waves=0, heavy_workgroups_per_cu=0):
-        super().__init__(workgroups_per_cu, chunk, split_steps, heavy_waves, heavy_workgroups_per_cu)
+    def __init__(self, workgroups_per_cu=0, chunk=0, split_steps=-1, heavy_waves=0, heavy_workgroups_per_cu=0,
+                 one_block_per_workgroup=0):
+        super().__init__(workgroups_per_cu, chunk, split_steps, heavy_waves, heavy_workgroups_per_cu,
+                         one_block_per_workgroup)
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -147,7 +147,9 @@ int get_schedule(int n, uint64_t need, hipStream_t stream, const orbg::Schedule*
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(ORBG_EHIP, "hipGetDevice failed");
-    uint64_t len = round_up_pow2(need);
+    // lengths up to 2^22 are powers of two (budgets share schedules); longer
+    // ones whole batches of 64
+    uint64_t len = need <= ORBG_SCHED_POW2_MAX ? round_up_pow2(need) : (need + 63) / 64 * 64;
     if (n < 63 && len > (1ull << n)) len = 1ull << n;
     std::lock_guard<std::mutex> lk(g_mu);
     auto key = std::make_tuple(dev, n, len);
@@ -235,12 +237,15 @@ orbg::LaunchParams resolve_params(const orbg_launch_params* p, bool ordered)
     r.split_steps = 64;
     r.heavy_waves = 8;
     r.heavy_wg_per_cu = 2;
+    r.naive = 0;
     if (p) {
         if (p->workgroups_per_cu > 0) r.wg_per_cu = p->workgroups_per_cu;
         if (p->chunk > 0) r.chunk = p->chunk;
         if (p->split_steps >= 0) r.split_steps = p->split_steps;
         if (p->heavy_waves > 0) r.heavy_waves = p->heavy_waves;
         if (p->heavy_workgroups_per_cu > 0) r.heavy_wg_per_cu = p->heavy_workgroups_per_cu;
+        r.naive = p->one_block_per_workgroup;
+        if (r.naive) r.split_steps = 0;
     }
     // the reordered prefix (64 steps) always stays in the light pass
     if (ordered && r.split_steps > 0 && r.split_steps < 64) r.split_steps = 64;
@@ -258,6 +263,8 @@ int check_params(const orbg_launch_params* p)
         return fail(ORBG_EINVAL, "heavy_waves = %d is not 0, 4, 8 or 16", p->heavy_waves);
     if (p->heavy_workgroups_per_cu < 0 || p->heavy_workgroups_per_cu > 16)
         return fail(ORBG_EINVAL, "heavy_workgroups_per_cu = %d outside [0, 16]", p->heavy_workgroups_per_cu);
+    if (p->one_block_per_workgroup != 0 && p->one_block_per_workgroup != 1)
+        return fail(ORBG_EINVAL, "one_block_per_workgroup = %d is not 0 or 1", p->one_block_per_workgroup);
     return ORBG_OK;
 }
 
@@ -317,7 +324,7 @@ int describe_1line(const CodeEntry* c, uint64_t need, hipStream_t st, orbg::Code
 int check_budget(uint64_t budget, int64_t batch)
 {
     if (budget < 1 || budget > ORBG_BUDGET_MAX)
-        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^22]", (unsigned long long)budget);
+        return fail(ORBG_EINVAL, "budget = %llu outside [1, 5 x 10^6]", (unsigned long long)budget);
     if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
     return ORBG_OK;
 }
@@ -393,6 +400,8 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
         return fail(ORBG_EINVAL, "a device buffer is NULL");
     if (order && n < 12) return fail(ORBG_EINVAL, "a batch order needs n >= 12 (got %d)", n);
+    if (oneline && budget > ORBG_BUDGET_MAX_1LINE)
+        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^22] for the 1-line order", (unsigned long long)budget);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CodeEntry* code = nullptr;
     if ((rc = get_code(H, n, k, &code))) return rc;
@@ -661,7 +670,7 @@ int orbg_schedule_export_1line(int n, uint64_t budget, int j0, uint64_t count, u
 {
     g_err.clear();
     if (n < 1 || n > ORBG_NMAX) return fail(ORBG_EINVAL, "n = %d outside [1, %d]", n, ORBG_NMAX);
-    if (budget < 1 || budget > ORBG_BUDGET_MAX || (n < 63 && budget > (1ull << n)))
+    if (budget < 1 || budget > ORBG_BUDGET_MAX_1LINE || (n < 63 && budget > (1ull << n)))
         return fail(ORBG_EINVAL, "budget = %llu out of range", (unsigned long long)budget);
     if (count > budget) return fail(ORBG_EINVAL, "count = %llu above the budget", (unsigned long long)count);
     if (j0 < -1 || j0 >= (1 << 20)) return fail(ORBG_EINVAL, "j0 = %d outside [-1, 2^20 - 1]", j0);

@@ -769,7 +769,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
              int chunk, int32_t* __restrict__ j0_out, int64_t row_limit, const int64_t* __restrict__ ids,
-             uint32_t t0)
+             uint32_t t0, int naive)
 {
     // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
     // m x nk words), then their columns (sum of n entries)
@@ -799,7 +799,6 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     int64_t lo = nblocks * home / ORBG_XCDS, hi = nblocks * (home + 1) / ORBG_XCDS, end = 0;
     unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(home);
     unsigned long long pend = 0;
-    if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
     // start of the next chunk (its end in `end`), or -1 when every slice is
     // drained.  Every cursor value goes through readfirstlane so that it stays
     // in scalar registers and the branches on it stay scalar.
@@ -852,14 +851,16 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         for (int64_t g = s; g < e; g += K) {
             float xs[K][NKMAX];
             int cis[K];
+            bool use[K];
             int64_t rows[K], oids[K];
             uint32_t first[K];
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
-                const bool ok = g + kk < e;
+                bool ok = g + kk < e;
                 int ci = 0;
                 int64_t row = 0, oid = 0;
                 if (ok) locate(g + kk, ci, row, oid);
+                use[kk] = ok;
                 cis[kk] = ci;
                 rows[kk] = row;
                 oids[kk] = oid;
@@ -873,7 +874,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int64_t b = g + kk;
-                if (b < e) {
+                if (use[kk]) {
                     const CodeDesc& c = codes.c[cis[kk]];
                     uint64_t hr[NKMAX];
                     if (HOIST) {
@@ -943,6 +944,17 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
     };
 
+    // One block per workgroup (the baseline a plain launch gives: no work
+    // counter, no chunks, no heavy pass): workgroup b decodes block b.
+    if (naive) {
+        if ((int64_t)blockIdx.x < nblocks) {
+            RowFetch<NKMAX> f;
+            fetch(f, (int64_t)blockIdx.x);
+            decode(f, (int64_t)blockIdx.x);
+        }
+        return;
+    }
+    if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
     for (int64_t s = uniform_i64(next_chunk()); s >= 0; s = uniform_i64(next_chunk())) {
         uint64_t left = screen(s, end);
         if (left == 0) continue;
@@ -1103,7 +1115,7 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
     const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
     light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
-        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit, a.ids, a.skip0 ? 1u : 0u);
+        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit, a.ids, a.skip0 ? 1u : 0u, a.p.naive);
 }
 
 template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
@@ -1118,6 +1130,11 @@ static void launch_heavy_g(const DecodeArgs& a, uint32_t split, hipStream_t stre
 template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE = false>
 static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
 {
+    if (a.p.naive) {                                    // one one-wave workgroup per block
+        if (a.nblocks > 0x7fffffffll) return hipErrorInvalidValue;
+        launch_light<NKMAX, ORDERED, S, MIXED, ONELINE>(a, a.nblocks, 1, 0u, stream);
+        return hipGetLastError();
+    }
     int64_t wgs = a.nblocks;
     const int64_t cap = (int64_t)a.cus * (a.p.wg_per_cu > 0 ? a.p.wg_per_cu : 32);
     if (wgs > cap) wgs = cap;

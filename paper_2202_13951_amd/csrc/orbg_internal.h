@@ -11,10 +11,14 @@
 #define ORBG_XCDS 8          // accelerator complex dies per MI355X (workgroups dealt round-robin)
 #define ORBG_COUNTER_STRIDE 32  // u64 stride between work counters (256 B apart)
 #define ORBG_MMAX 64         // largest redundancy n - k (syndromes are one u64)
-#define ORBG_BUDGET_MAX (1ull << 22)
+#define ORBG_BUDGET_MAX 5000000ull    // the abandonment threshold the paper uses (Sec. IV-A)
+#define ORBG_BUDGET_MAX_1LINE (1ull << 22)
+#define ORBG_SCHED_POW2_MAX (1ull << 22)  // schedules up to this length are rounded up to a power of two
 #define ORBG_LOW_RANKS 8     // ranks 1..8 are flipped through a per-block subset table
 #define ORBG_HIGH_SLOTS 7    // ranks above 8 held by one entry (bytes 1..7)
 #define ORBG_WLEVEL_PACKED 99  // every pattern of logistic weight <= 99 has at most 7 ranks above 8
+#define ORBG_WLEVEL_SCHED 100  // the schedule also takes logistic weight 100 up to its one pattern
+                               // with 8 ranks above 8, {9, ..., 16}, the last of its (W, w) class
 #define ORBG_SCHED_PAD 4        // zero batches after a schedule's last batch
 
 namespace orbg {

@@ -38,6 +38,7 @@ struct LaunchParams {
     int split_steps;           // light pass stops a block after this many 64-query steps (0 = never)
     int heavy_waves;           // waves that share one heavy block (4, 8 or 16)
     int heavy_wg_per_cu;       // heavy pass: workgroups per compute unit
+    int naive;                 // 1: one one-wave workgroup per block, no work counter, no heavy pass
 };
 
 struct DecodeArgs {

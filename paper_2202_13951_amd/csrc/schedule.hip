@@ -13,7 +13,12 @@
 // the syndromes of all 256 subsets of the eight least reliable bits), bytes 1..7
 // are the flipped ranks above 8 in increasing order, 0 marking an unused slot.
 // A pattern of logistic weight at most 99 never flips more than seven ranks
-// above 8 (9 + 10 + ... + 16 = 100), which bounds the schedule length.
+// above 8 (9 + 10 + ... + 16 = 100); at logistic weight 100 only {9, ..., 16}
+// flips eight, and it is the last pattern of its class (W = 100, w = 8: the
+// lexicographically largest), so the schedule runs up to the pattern before it:
+// all patterns of logistic weight <= 99 (4,827,382 for n >= 99) and those of
+// weight 100 with w <= 7 and the first ones with w = 8, which covers the paper's
+// abandonment threshold of 5 x 10^6 queries (Sec. IV-A) for every n >= 100.
 //
 // Built by three kernels:
 //   1. class_count_kernel: w-subsets of {1..n} with sum W (a subset-sum count),
@@ -62,9 +67,15 @@ class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int
     // lay the classes out: W ascending, w ascending, until len entries exist
     uint64_t off = 0;
     int nc = 0, wlast = 0;
-    for (int Wl = 0; Wl <= ORBG_WLEVEL_PACKED && off < len; ++Wl) {
+    for (int Wl = 0; Wl <= ORBG_WLEVEL_SCHED && off < len; ++Wl) {
         for (int w = 0; w <= ORBG_WMAX_H && off < len; ++w) {
-            const uint64_t c = N[w][Wl];
+            uint64_t c = N[w][Wl];
+            if (Wl > ORBG_WLEVEL_PACKED) {
+                // weight 100: classes up to w = 8 without its last pattern {9..16}
+                // (present when n >= 16); what follows it cannot be represented
+                if (w > ORBG_HIGH_SLOTS + 1) break;
+                if (w == ORBG_HIGH_SLOTS + 1 && n >= 16) c -= 1;
+            }
             if (c == 0) continue;
             classes[nc].W = Wl;
             classes[nc].w = w;
@@ -75,7 +86,7 @@ class_count_kernel(int n, uint64_t len, ClassInfo* classes, int* nclass_out, int
             wlast = Wl;
         }
     }
-    // off < len here means the schedule would need W > WCAP or w > WMAX_H
+    // off < len here means the schedule would need a pattern it cannot hold
     *nclass_out = (off >= len) ? nc : -nc - 1;
     *wlast_out = wlast;
 }
@@ -211,8 +222,8 @@ int orbg_build_schedule(int n, uint64_t len, hipStream_t stream, Schedule* out, 
     }
     int nclass = host_small[0];
     if (nclass < 0) {
-        snprintf(err, errlen, "schedule: %llu patterns need a logistic weight above %d",
-                 (unsigned long long)len, ORBG_WLEVEL_PACKED);
+        snprintf(err, errlen, "schedule: %llu patterns reach past the pattern {9, ..., 16} of logistic "
+                 "weight %d", (unsigned long long)len, ORBG_WLEVEL_SCHED);
         (void)hipFree(d_classes); (void)hipFree(d_small);
         return -1;
     }

@@ -172,3 +172,43 @@ def test_bch_full_size_sampled(gpu_device):
     ok = torch.from_numpy(gab == 0).to(gpu_device)
     syn = (torch.from_numpy(gcw).to(gpu_device).float() @ Hf.T).remainder(2)
     assert not syn[ok].any()
+
+
+W99_PATTERNS = 4827382          # patterns of logistic weight <= 99 for n >= 99 (the coefficients of eq. (intpart))
+
+
+@pytest.mark.parametrize("n", [64, 100, 256])
+def test_schedule_to_the_papers_threshold(gpu_device, n):
+    """The schedule for the paper's abandonment threshold of 5 x 10^6 queries
+    (Sec. IV-A) equals the oracle's order entry for entry: all patterns of
+    logistic weight <= 99, then those of weight 100 (which the schedule holds up
+    to the one pattern with eight ranks above 8)."""
+    count = 5 * 10 ** 6
+    print(f"schedule n={n} count={count}", flush=True)
+    got = binding.orbg_schedule_export(n, count).astype(np.int32)
+    want = O.order_prefix_array(n, count)
+    assert got.shape == want.shape == (count, 16)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert bad.size == 0, f"first differing entry {bad[0]}: gpu {got[bad[0]]} oracle {want[bad[0]]}"
+    assert int(got[-1].sum()) == 100
+    if n >= 99:
+        assert int(got[W99_PATTERNS - 1].sum()) == 99 and int(got[W99_PATTERNS].sum()) == 100
+
+
+def test_rlc256_234_at_the_papers_threshold(gpu_device):
+    """RLC(256,234) (22 parity bits: the length and redundancy of the paper's
+    CA-Polar[256,234]) at 4 dB with the paper's budget of 5 x 10^6 queries:
+    every search that ends among the weight-100 patterns, some abandoned ones
+    and a random sample, against the oracle element by element."""
+    print("rlc256_234 budget 5e6", flush=True)
+    H, G = codes.code("rlc256_234")
+    N, budget = 3000, 5 * 10 ** 6
+    llr, _ = channel.awgn_llr(G, N, 4.0, seed=606)
+    gcw, gq, gab = _gpu_decode(H, llr, budget, gpu_device)
+    assert ((gq >= 1) & (gq <= budget)).all() and (gq[gab == 1] == budget).all()
+    w100 = np.nonzero((gq > W99_PATTERNS) & (gab == 0))[0]
+    print(f"{w100.size} searches end among the weight-100 patterns, {int(gab.sum())} abandoned", flush=True)
+    assert w100.size >= 1
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([w100[:8], np.nonzero(gab == 1)[0][:4], rng.choice(N, 32, replace=False)]))
+    _assert_same((gcw[idx], gq[idx], gab[idx]), O.decode(H, llr[idx], budget, THREADS), "rlc256 5e6")
