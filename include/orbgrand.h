@@ -166,12 +166,12 @@ int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t
  * product of the per-segment partial sets (segment 1 outermost; each partial
  * set by Hamming weight, then Landslide order).  Same H, llr, codeword,
  * queries, abandoned layouts and rules as orbg_decode.
- * Limits: 1 <= n <= 256, 1 <= n - k <= 64, 1 <= segments <= 4, jdiv 0 or 1,
- * 1 <= budget <= 2^20 (within that budget no query has more than 20 flips in a
- * segment, which bounds the device tables).  segments_out: DEVICE i32 per
- * block, the number of lines the fit used, or NULL.  The first call on a device
- * builds an 88 MB table of subset counts (allocates and synchronises
- * `stream`).  Errors: ORBG_EINVAL for arguments outside these limits, as
+ * Limits: 1 <= n <= 512, 1 <= n - k <= 64, 1 <= segments <= 4, jdiv 0 or 1,
+ * 1 <= budget <= 5 x 10^6 (the threshold of Sec. IV-A; within that budget no
+ * query has more than 22 flips, which bounds the device tables).  segments_out:
+ * DEVICE i32 per block, the number of lines the fit used, or NULL.  The first
+ * call on a device builds a 193 MB table of subset counts (allocates and
+ * synchronises `stream`).  Errors: ORBG_EINVAL for arguments outside these limits, as
  * orbg_decode otherwise.
  */
 int orbg_decode_mline(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,

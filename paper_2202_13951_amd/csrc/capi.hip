@@ -560,7 +560,7 @@ int orbg_decode_mline(const uint8_t* H, const float* llr, int n, int k, uint64_t
         return fail(ORBG_EINVAL, "segments = %d outside [1, %d]", segments, ORBG_ML_MSEG);
     if (jdiv != 0 && jdiv != 1) return fail(ORBG_EINVAL, "jdiv = %d is not 0 or 1", jdiv);
     if (budget < 1 || budget > ORBG_ML_BUDGET_MAX)
-        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^20] for the m-line order", (unsigned long long)budget);
+        return fail(ORBG_EINVAL, "budget = %llu outside [1, 5 x 10^6] for the m-line order", (unsigned long long)budget);
     if (batch < 0) return fail(ORBG_EINVAL, "batch = %lld is negative", (long long)batch);
     if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
         return fail(ORBG_EINVAL, "a device buffer is NULL");

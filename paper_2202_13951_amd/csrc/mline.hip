@@ -1,7 +1,7 @@
 // Full (m-line) ORBGRAND decode kernel for gfx950 (Sec. III-D; fit of Sec. III-E).
 //
 // Per block, one wave:
-//   1. the LLR row (n <= 256: up to four elements per lane), hard decision and
+//   1. the LLR row (n <= 512: up to eight elements per lane), hard decision and
 //      base syndrome s0 (Sec. III-A); s0 == 0 is query 1;
 //   2. the full reliability order: keys (IEEE bits of |LLR|) << 32 | index sorted
 //      ascending by a register bitonic network; h_r = column of rank r, pi_r its
@@ -28,18 +28,22 @@
 //      in order;
 //   5. codeword, queries, abandon flag; optionally the block's segment count.
 //
-// Exactness limits (checked by the host): n <= 256, n - k <= 64, m <= 4,
-// budget <= 2^20.  A pattern with 21 or more flips inside one segment comes
-// after all 2^21 - 1 patterns made of proper subsets of its flips (each weighs
-// less, or the same with fewer flips, since every rank but rank 1 weighs at
-// least 1), so no query within 2^20 has more than 20 flips in a segment.  Nor
-// does one reach a partial logistic weight of 4096 or more: that needs at least
-// 17 flips in a segment of 205 ranks or more, and the patterns that differ only
-// there by as many flips with a smaller sum (over 10^24, those within the first
-// 200 ranks alone) all weigh less.  The count table covers w <= 20 and partial
-// weights below 4096; the order restricted to them agrees with the full order
-// on its first 2^20 patterns, and every division below has operands under 2^32
-// (4095 times a slope of at most 2^20).
+// Exactness limits (checked by the host): n <= 512, n - k <= 64, m <= 4,
+// budget <= 5 x 10^6.  Every rank but rank 1 weighs at least 1 and rank 1 at
+// least 0, so dropping flips from a pattern gives one that comes earlier (less
+// weight, or the same weight, split and other segments with fewer flips in
+// segment 1, which the order puts first).  A pattern with f flips therefore
+// has the 2^f - 1 patterns made of proper subsets of its flips before it: no
+// query within 5 x 10^6 < 2^23 - 1 has more than 22 flips.  Nor does one reach
+// a relative logistic weight (sum of positions inside a segment) of 4096 or
+// more: with w flips that needs w floor(4095 / w) < 4096 <= the segment's
+// largest sum, so the segment is longer than K = floor(4095 / w), and the
+// C(K, w) patterns that replace those w flips by w positions out of 1..K
+// (w <= 22: at least C(186, 22), and C(455, 9) for the fewest flips a segment
+// of 512 ranks needs) all weigh less.  The count table covers w <= 22 and
+// relative weights below 4096; the order restricted to them agrees with the
+// full order on its first 5 x 10^6 patterns, and every division below has
+// operands under 2^32 (4095 times a slope of at most 2^20).
 #include "orbg_device.h"
 #include "orbg_internal.h"
 #include "orbg_mline.h"
@@ -48,7 +52,7 @@ namespace orbg {
 
 namespace {
 
-constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..20
+constexpr int WL = ORBG_ML_WMAX;          // partial Hamming weights 0..22
 constexpr int SL = ORBG_ML_SMAX;          // partial logistic weights 0..4095
 constexpr int64_t NONE = INT64_MAX;
 
@@ -104,7 +108,7 @@ __device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
 // below stop at the first w whose smallest weight passes x.
 __device__ __forceinline__ int64_t min_weight(const Seg& g, int w) { return (int64_t)w * g.J + g.B * lw_min(w); }
 
-// Number of partial patterns (at most 20 flips) of the segment with partial
+// Number of partial patterns (at most 22 flips) of the segment with partial
 // weight x; the empty one has weight 0.
 __device__ uint64_t seg_count(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x)
 {
@@ -143,7 +147,7 @@ __device__ int64_t seg_next(const Seg& g, int64_t x)
     return best;
 }
 
-// Can the segment take partial weight x (some partial Hamming weight <= 20)?
+// Can the segment take partial weight x (some partial Hamming weight <= 22)?
 __device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
 {
     if (x == 0) return true;
@@ -172,7 +176,7 @@ __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
 
 // A split waiting to be tested (LDS ring of ORBG_ML_QCAP entries): its partial
 // weights, partial-set sizes (saturated at 2^32 - 1, exact for product indices
-// below 2^20), the first product element not yet tested and the number of
+// below the budget), the first product element not yet tested and the number of
 // elements to test (the product size, cut at the budget).
 struct QEntry {
     int64_t a[ORBG_ML_MSEG];
@@ -253,7 +257,7 @@ template <int M, typename F>
 __device__ __forceinline__ void unrank_product(const Seg (&seg)[M], const uint32_t* tbl, const int64_t (&a)[M],
                                                const uint32_t (&cnt)[M], uint32_t u, F&& emit)
 {
-    // u < 2^20: a radix above u leaves the digit u and quotient 0
+    // u < 2^23: a radix above u leaves the digit u and quotient 0
     uint32_t t[M];
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
@@ -322,7 +326,9 @@ __device__ void flush(Walk<M>& c, bool final)
             c.stop = true;
             if (lane == wl) {
                 int nw = 0;
-                unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) { c.win[nw++] = (uint16_t)r; });
+                unrank_product(c.seg, c.tbl, a, cn, idx, [&](int r) {
+                    if (nw < ORBG_ML_WINCAP) c.win[nw++] = (uint16_t)r;
+                });
                 c.win[ORBG_ML_WINCAP] = (uint16_t)nw;
             }
             wave_lds_sync();
@@ -448,8 +454,8 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
 
 // Reliability weights in increasing order, each one's splits queued and tested.
 // No weight left (NONE) is only possible once the query limit is reached (the
-// limit is at most 2^n, and for n >= 21 the order holds more than 2^20
-// patterns), so the queue has been tested by then.
+// limit is at most 2^n, and the restricted order holds min(2^n, the budget)
+// patterns at least), so the queue has been tested by then.
 template <int M>
 __device__ void walk(Walk<M>& c)
 {
@@ -481,11 +487,12 @@ __device__ __forceinline__ bool round_half_up(float x, int64_t& out)
     return true;
 }
 
-// LDS of one wave.
+// LDS of one wave, for codes of at most LC ranks.
+template <int LC>
 struct MlLds {
-    uint64_t h[ORBG_ML_LMAX + 1];       // h[r] = column of rank r
-    float L[ORBG_ML_LMAX + 1];          // L[r] = |LLR| of rank r
-    uint16_t pi[ORBG_ML_LMAX + 1];      // pi[r] = received index of rank r
+    uint64_t h[LC + 1];                 // h[r] = column of rank r
+    float L[LC + 1];                    // L[r] = |LLR| of rank r
+    uint16_t pi[LC + 1];                // pi[r] = received index of rank r
     int anc[ORBG_ML_MSEG + 2];          // anchor ranks, ascending
     uint16_t win[ORBG_ML_WINCAP + 1];   // winner's ranks, then their count
     QEntry Q[ORBG_ML_QCAP];             // splits waiting to be tested
@@ -509,8 +516,8 @@ __device__ __forceinline__ void model_basic(Model& md, int n)
 
 // Fit with at most mreq segments (L in LDS, ranks 1..n; h = n/2 <= 32 NK).
 // Wave-uniform result.
-template <int NK>
-__device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
+template <int NK, typename Lds>
+__device__ Model fit_model(Lds& S, int n, int mreq, bool jdiv)
 {
     const int lane = lane_id();
     Model md;
@@ -521,7 +528,7 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
     wave_lds_sync();
     int na = 2;
     for (int it = 1; it < mreq; ++it) {
-        // candidate ranks j = l + 1 (and l + 65 when h can pass 64) of lane l,
+        // candidate ranks j = l + 1 + 64 t of lane l (t < NK / 2: h <= 32 NK),
         // each strictly between two adjacent anchors: largest gap, smallest
         // rank on ties, as the max of (gap bits, 0xffff - j)
         auto gap_key = [&](int j) -> uint64_t {
@@ -540,8 +547,9 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
             return ((uint64_t)__float_as_uint(gap) << 32) | (uint64_t)(0xffff - j);
         };
         uint64_t key = gap_key(lane + 1);
-        if constexpr (NK > 2) {
-            const uint64_t k2 = gap_key(lane + 1 + ORBG_WAVE);
+#pragma unroll
+        for (int t = 1; t < NK / 2; ++t) {
+            const uint64_t k2 = gap_key(lane + 1 + t * ORBG_WAVE);
             key = k2 > key ? k2 : key;
         }
 #pragma unroll
@@ -610,8 +618,8 @@ __device__ Model fit_model(MlLds& S, int n, int mreq, bool jdiv)
     return r;
 }
 
-template <int M>
-__device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint64_t s0, uint32_t limit,
+template <int M, typename Lds>
+__device__ void decode_walk(const Model& md, const uint32_t* tbl, Lds& S, uint64_t s0, uint32_t limit,
                             bool& found, uint32_t& q, int& nwin)
 {
     Walk<M> c;
@@ -649,7 +657,7 @@ __device__ void decode_walk(const Model& md, const uint32_t* tbl, MlLds& S, uint
 template <int NK>
 __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(NK <= 2 ? 5 : 1))) mline_kernel(MlineArgs a)
 {
-    __shared__ MlLds S;
+    __shared__ MlLds<NK * ORBG_WAVE> S;
     const int lane = lane_id();
     const int n = a.n;
     // rows of H, one per lane (lanes >= n - k hold zeros)
@@ -698,7 +706,7 @@ __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(
             m_used = md.m;
             // queries to make: the budget, at most all 2^n patterns (they hold
             // a member, so the walk ends at a hit before running out)
-            const uint32_t limit = (n < 21 && a.budget > (1u << n)) ? (1u << n) : a.budget;
+            const uint32_t limit = (n < 32 && a.budget > (1u << n)) ? (1u << n) : a.budget;
             if (s0 == 0) {
                 found = true;
                 q = 1;
@@ -777,7 +785,8 @@ hipError_t launch_mline(const MlineArgs& a, int grid, hipStream_t stream)
     if (a.nblocks <= 0) return hipSuccess;
     if (a.n <= ORBG_WAVE) mline_kernel<1><<<grid, ORBG_WAVE, 0, stream>>>(a);
     else if (a.n <= 2 * ORBG_WAVE) mline_kernel<2><<<grid, ORBG_WAVE, 0, stream>>>(a);
-    else mline_kernel<4><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    else if (a.n <= 4 * ORBG_WAVE) mline_kernel<4><<<grid, ORBG_WAVE, 0, stream>>>(a);
+    else mline_kernel<8><<<grid, ORBG_WAVE, 0, stream>>>(a);
     return hipGetLastError();
 }
 

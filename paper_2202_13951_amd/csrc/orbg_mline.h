@@ -3,12 +3,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define ORBG_ML_WMAX 20          // flips per segment the order reaches within the budget limit
+#define ORBG_ML_WMAX 22          // flips per pattern the order reaches within the budget limit
 #define ORBG_ML_SMAX 4096        // partial logistic weights 0..4095 (the order reaches no larger one)
-#define ORBG_ML_LMAX 256         // largest code length (and segment length)
+#define ORBG_ML_LMAX 512         // largest code length (and segment length)
 #define ORBG_ML_MSEG 4           // largest number of segments
-#define ORBG_ML_WINCAP 80        // flips of one pattern: at most 20 per segment
-#define ORBG_ML_BUDGET_MAX 1048576  // largest query budget (2^20)
+#define ORBG_ML_WINCAP 22        // flips of one pattern
+#define ORBG_ML_BUDGET_MAX 5000000  // largest query budget
 #define ORBG_ML_QCAP 64          // queued splits: fewer than 64 untested patterns plus one
 
 namespace orbg {
@@ -18,7 +18,7 @@ struct MlineArgs {
     int n;
     int m;                     // n - k
     const uint64_t* cols;      // n packed parity-check columns
-    const uint64_t* rows;      // m x nk packed rows (nk = 1, 2, 4 for n <= 64, 128, 256)
+    const uint64_t* rows;      // m x nk packed rows (nk = 1, 2, 4, 8 for n <= 64, 128, 256, 512)
     int64_t nblocks;
     uint32_t budget;
     int mseg;                  // largest number of segments of the fit

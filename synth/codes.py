@@ -116,6 +116,7 @@ def code(name: str):
         "rlc256_240": lambda: rlc_H(256, 240, seed=256240),
         "rlc256_234": lambda: rlc_H(256, 234, seed=256234),
         "rlc128_105": lambda: rlc_H(128, 105, seed=128105),
+        "rlc512_490": lambda: rlc_H(512, 490, seed=512490),
     }
     H = table[name]()
     return H, generator_matrix(H)

@@ -166,13 +166,13 @@ def test_1line_export_argument_errors(n, budget, j0, count, msg):
 
 @pytest.mark.parametrize("n,k,budget,seg,jdiv,bufs,msg", [
     (0, 0, 10, 2, 0, True, "n = 0"),
-    (257, 240, 10, 2, 0, True, "n = 257"),
+    (513, 500, 10, 2, 0, True, "n = 513"),
     (100, 30, 10, 2, 0, True, "n - k = 70"),
     (32, 26, 10, 0, 0, True, "segments = 0"),
     (32, 26, 10, 5, 0, True, "segments = 5"),
     (32, 26, 10, 2, 2, True, "jdiv = 2"),
     (32, 26, 0, 2, 0, True, "budget = 0"),
-    (32, 26, (1 << 20) + 1, 2, 0, True, "budget = 1048577"),
+    (32, 26, 5 * 10 ** 6 + 1, 2, 0, True, "budget = 5000001"),
     (32, 26, 100, 2, 0, False, "device buffer is NULL"),
 ])
 def test_mline_argument_errors(n, k, budget, seg, jdiv, bufs, msg):

@@ -97,13 +97,50 @@ def test_one_segment_is_the_1line_decoder(gpu_device):
     (33, 20, 30000, 2.0, 4, False), (63, 50, 20000, 2.5, 3, False), (64, 40, 65536, 2.0, 2, True),
     (65, 52, 20000, 2.5, 4, False), (100, 36, 3000, 2.5, 3, False), (128, 80, 5000, 3.0, 4, True),
     (128, 64, 2000, 3.0, 2, False), (129, 100, 3000, 3.0, 3, False), (200, 170, 3000, 3.5, 2, True),
-    (256, 192, 2000, 3.0, 4, False)])
+    (256, 192, 2000, 3.0, 4, False), (257, 200, 2000, 3.0, 3, False), (300, 250, 3000, 3.5, 4, True),
+    (448, 400, 3000, 3.5, 2, False), (511, 490, 3000, 4.0, 3, False), (512, 448, 2000, 3.5, 4, True)])
 def test_ragged_lengths(gpu_device, n, k, budget, ebn0, segments, jdiv):
-    """Ragged lengths with one, two and four keys per lane, n - k up to 64."""
+    """Ragged lengths with one, two, four and eight keys per lane, n - k up to 64."""
     H = codes.rlc_H(n, k, seed=n * 7 + k)
     G = codes.generator_matrix(H)
     llr, _ = channel.awgn_llr(G, 300, ebn0, seed=n + 5 * k)
     _both(H, llr, budget, segments, jdiv, gpu_device, f"n={n} k={k}")
+
+
+@pytest.mark.parametrize("segments,jdiv", [(1, False), (2, False), (3, False), (4, False), (3, True)])
+def test_rlc512_490(gpu_device, segments, jdiv):
+    """Length 512 with 22 parity bits (the length and redundancy of the paper's
+    CA-Polar[512,490], Sec. IV-A): eight keys per lane, fit candidates up to
+    rank 256."""
+    H, G = codes.code("rlc512_490")
+    llr, _ = channel.awgn_llr(G, 256, 5.0, seed=5124)
+    want = _both(H, llr, 10 ** 5, segments, jdiv, gpu_device, "rlc512")
+    assert want[3].max() == segments
+
+
+def _threshold_sample(q, ab, n_deep, rng):
+    deep = np.nonzero((q > (1 << 20)) & (ab == 0))[0]
+    return deep, np.unique(np.concatenate([deep[:n_deep], np.nonzero(ab == 1)[0][:3],
+                                           rng.choice(q.size, 24, replace=False)]))
+
+
+@pytest.mark.parametrize("name,ebn0,segments,N", [("rlc256_234", 4.0, 3, 2000), ("rlc512_490", 4.5, 2, 600)])
+def test_at_the_papers_threshold(gpu_device, name, ebn0, segments, N):
+    """The paper's budget of 5 x 10^6 queries (Sec. IV-A) on the 22-parity-bit
+    codes of length 256 and 512: every search that ends past 2^20 queries (up to
+    eight), some abandoned ones and a random sample, against the oracle element
+    by element; properties of every block."""
+    print(f"m-line {name} budget 5e6", flush=True)
+    H, G = codes.code(name)
+    budget = 5 * 10 ** 6
+    llr, _ = channel.awgn_llr(G, N, ebn0, seed=707)
+    cw, q, ab, ms = _gpu(H, llr, budget, segments, False, gpu_device)
+    assert ((q >= 1) & (q <= budget)).all() and (q[ab == 1] == budget).all()
+    deep, idx = _threshold_sample(q, ab, 8, np.random.default_rng(2))
+    print(f"{deep.size} searches end past 2^20 queries, {int(ab.sum())} abandoned", flush=True)
+    assert deep.size >= 1
+    _assert_same((cw[idx], q[idx], ab[idx], ms[idx]), _oracle(H, llr[idx], budget, segments, False),
+                 f"{name} 5e6")
 
 
 def test_special_values_and_fit_edges(gpu_device):
@@ -157,6 +194,8 @@ def test_budget_edges(gpu_device):
         want = _both(H, llr, budget, 3, False, gpu_device, "budget edges")
     assert want[2].sum() > 0
     want = _both(H, llr[:40], 1 << 20, 2, False, gpu_device, "budget 2^20")
+    want = _both(H, llr[40:64], 5 * 10 ** 6, 3, False, gpu_device, "budget 5e6")
+    assert (want[1] > (1 << 20)).any()
 
 
 def test_empty_batch(gpu_device):
@@ -165,9 +204,12 @@ def test_empty_batch(gpu_device):
     cw, q, ab, ms = binding.orbg_decode_mline(H, llr, 100, 3)
     torch.cuda.synchronize()
     assert cw.shape == (0, 32) and ms.shape == (0,)
-    H300 = codes.rlc_H(300, 280, seed=3)
-    with pytest.raises(binding.OrbgError):                    # n above 256
-        binding.orbg_decode_mline(H300, torch.zeros((4, 300), dtype=torch.float32, device=gpu_device), 100, 2)
+    H520 = codes.rlc_H(520, 500, seed=3)
+    with pytest.raises(binding.OrbgError):                    # n above 512
+        binding.orbg_decode_mline(H520, torch.zeros((4, 520), dtype=torch.float32, device=gpu_device), 100, 2)
+    with pytest.raises(binding.OrbgError):                    # budget above 5 x 10^6
+        binding.orbg_decode_mline(H, torch.zeros((4, 32), dtype=torch.float32, device=gpu_device),
+                                  5 * 10 ** 6 + 1, 2)
 
 
 def test_bch_full_size_sampled(gpu_device):
