@@ -74,39 +74,56 @@ __device__ __forceinline__ uint32_t subset_count(const uint32_t* __restrict__ tb
 }
 
 __device__ __forceinline__ int64_t lw_min(int64_t w) { return w * (w + 1) / 2; }
-__device__ __forceinline__ int64_t lw_max(int64_t w, int64_t len) { return w * len - w * (w - 1) / 2; }
 
-// One segment of the model: offset J_{i-1}, slope beta_i, first rank - 1, length.
+// One segment of the model: offset J_{i-1}, slope beta_i, first rank - 1,
+// length, and rcp = floor((2^32 - 1) / beta_i) for division by beta_i.
 struct Seg {
     int64_t J, B;
     int off, len;
+    uint32_t rcp;
 };
 
 __device__ __forceinline__ int wcap(const Seg& g) { return g.len < WL ? g.len : WL; }
 
-// Largest relative logistic weight of w flips in the segment that the order
-// reaches (the segment's own bound, capped below 4096).
-__device__ __forceinline__ int64_t lw_top(int64_t w, int64_t len)
+// d / beta and d % beta for d < 2^32 by one high multiply: the error of rcp
+// against 2^32 / beta is at most 1, so floor(d rcp / 2^32) is the quotient or
+// one less, and one remainder test corrects it.
+__device__ __forceinline__ uint32_t seg_div(const Seg& g, uint32_t d, uint32_t& rem)
 {
-    const int64_t m = lw_max(w, len);
-    return m < SL - 1 ? m : SL - 1;
+    const uint32_t b = (uint32_t)g.B;
+    uint32_t q = __umulhi(d, g.rcp);
+    uint32_t r = d - q * b;
+    if (r >= b) {
+        ++q;
+        r -= b;
+    }
+    rem = r;
+    return q;
 }
 
-// Relative logistic weight of w >= 1 flips with partial weight x, or -1.  The
-// range test comes first, so the one division left has operands below 2^32.
-__device__ __forceinline__ int64_t rel_weight(const Seg& g, int64_t x, int w)
-{
-    const int64_t r = x - (int64_t)w * g.J;
-    if (r < lw_min(w) * g.B || r > lw_top(w, g.len) * g.B) return -1;
-    if (g.B == 1) return r;
-    const uint32_t rr = (uint32_t)r, bb = (uint32_t)g.B, wp = rr / bb;
-    return wp * bb == rr ? (int64_t)wp : -1;
-}
-
-// Smallest partial weight of w flips: w J + beta w(w+1)/2.  It grows strictly
-// with w (by J + beta (w+1) >= beta w > 0, as J >= -beta), so the loops over w
-// below stop at the first w whose smallest weight passes x.
-__device__ __forceinline__ int64_t min_weight(const Seg& g, int w) { return (int64_t)w * g.J + g.B * lw_min(w); }
+// The partial weights of w flips in a segment run from lo_w = w J + beta
+// w(w+1)/2 to hi_w = w J + beta min(w len - w(w-1)/2, 4095) in steps of beta
+// (relative weight, the sum of the positions inside the segment, from
+// w(w+1)/2 up, capped below 4096).  lo_w grows strictly with w (by J +
+// beta (w+1) >= beta w > 0, as J >= -beta), so a scan over w for a weight x
+// stops at the first lo_w above x.  hi_w - lo_w < 4095 beta <= 2^32 - 2^20
+// (beta <= 2^20): offsets inside one range are 32-bit.  SegScan steps through
+// w = 1, 2, ... and keeps lo_w, hi_w.
+struct SegScan {
+    int64_t wJ, bs, lo, hi;
+    int w, lmax;
+    __device__ __forceinline__ explicit SegScan() : wJ(0), bs(0), lo(0), hi(0), w(0), lmax(0) {}
+    __device__ __forceinline__ void next(const Seg& g)
+    {
+        ++w;
+        wJ += g.J;
+        bs += g.B * w;                         // beta w(w+1)/2
+        lo = wJ + bs;
+        lmax += g.len - (w - 1);               // w len - w(w-1)/2
+        const int top = lmax < SL - 1 ? lmax : SL - 1;
+        hi = wJ + (int64_t)((uint32_t)g.B * (uint32_t)top);
+    }
+};
 
 // Number of partial patterns (at most 22 flips) of the segment with partial
 // weight x; the empty one has weight 0.
@@ -114,37 +131,71 @@ __device__ uint64_t seg_count(const uint32_t* __restrict__ tbl, const Seg& g, in
 {
     uint64_t c = x == 0 ? 1u : 0u;
     const int wc = wcap(g);
-    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w) {
-        const int64_t wp = rel_weight(g, x, w);
-        if (wp >= 0) c += subset_count(tbl, g.len, w, wp);
+    SegScan sc;
+    for (int w = 1; w <= wc; ++w) {
+        sc.next(g);
+        if (sc.lo > x) break;
+        if (x <= sc.hi) {
+            uint32_t rem;
+            const uint32_t q = seg_div(g, (uint32_t)(x - sc.lo), rem);
+            if (rem == 0) c += subset_count(tbl, g.len, w, lw_min(w) + q);
+        }
     }
     return c;
 }
 
-// Smallest partial weight >= x the segment can take (NONE if none).
+// Smallest partial weight >= x the segment can take (NONE if none).  In range
+// w, the smallest weight >= x is lo_w + ceil((x - lo_w) / beta) beta, with
+// x - lo_w + beta - 1 < 2^32.
 __device__ int64_t seg_next(const Seg& g, int64_t x)
 {
     if (x <= 0) return 0;
     int64_t best = NONE;
     const int wc = wcap(g);
+    SegScan sc;
     for (int w = 1; w <= wc; ++w) {
-        const int64_t lo = lw_min(w), hi = lw_top(w, g.len), need = x - (int64_t)w * g.J;
-        int64_t wp;
-        if (need <= lo * g.B) {
-            // the smallest weight of w flips is >= x; larger w only give more
-            const int64_t c = min_weight(g, w);
-            if (c < best) best = c;
+        sc.next(g);
+        if (sc.lo >= x) {
+            // larger w only give more
+            best = sc.lo < best ? sc.lo : best;
             break;
-        } else if (need > hi * g.B) {
-            continue;                                  // ceil(need / B) > hi
-        } else {
-            const uint32_t nn = (uint32_t)need, bb = (uint32_t)g.B;      // nn + bb - 1 < 2^32
-            wp = g.B == 1 ? need : (int64_t)((nn + bb - 1u) / bb);
         }
-        const int64_t c = (int64_t)w * g.J + g.B * wp;
-        if (c < best) best = c;
+        if (x <= sc.hi) {
+            uint32_t rem;
+            const uint32_t q = seg_div(g, (uint32_t)(x - sc.lo) + (uint32_t)g.B - 1u, rem);
+            const int64_t c = sc.lo + (int64_t)q * g.B;
+            best = c < best ? c : best;
+        }
     }
     return best;
+}
+
+// Both of the above at once for y >= 0: the count at y and the smallest weight
+// above y (the smallest in range w above y is lo_w + (floor((y - lo_w) / beta)
+// + 1) beta, if that is <= hi_w).
+__device__ void seg_count_next(const uint32_t* __restrict__ tbl, const Seg& g, int64_t y, uint64_t& cnt,
+                               int64_t& nxt)
+{
+    uint64_t c = y == 0 ? 1u : 0u;
+    int64_t best = NONE;
+    const int wc = wcap(g);
+    SegScan sc;
+    for (int w = 1; w <= wc; ++w) {
+        sc.next(g);
+        if (sc.lo > y) {
+            best = sc.lo < best ? sc.lo : best;
+            break;
+        }
+        if (y <= sc.hi) {
+            uint32_t rem;
+            const uint32_t q = seg_div(g, (uint32_t)(y - sc.lo), rem);
+            if (rem == 0) c += subset_count(tbl, g.len, w, lw_min(w) + q);
+            const int64_t up = sc.lo + (int64_t)(q + 1u) * g.B;
+            if (up <= sc.hi) best = up < best ? up : best;
+        }
+    }
+    cnt = c;
+    nxt = best;
 }
 
 // Can the segment take partial weight x (some partial Hamming weight <= 22)?
@@ -152,9 +203,89 @@ __device__ __forceinline__ bool seg_member(const Seg& g, int64_t x)
 {
     if (x == 0) return true;
     const int wc = wcap(g);
-    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w)
-        if (rel_weight(g, x, w) >= 0) return true;
+    SegScan sc;
+    for (int w = 1; w <= wc; ++w) {
+        sc.next(g);
+        if (sc.lo > x) break;
+        if (x <= sc.hi) {
+            uint32_t rem;
+            (void)seg_div(g, (uint32_t)(x - sc.lo), rem);
+            if (rem == 0) return true;
+        }
+    }
     return false;
+}
+
+// Minimum of an i64 over the wave, wave-uniform (all lanes active): quad
+// swaps, half-row and row mirrors inside each 16-lane row, then the four rows.
+__device__ __forceinline__ int64_t dpp_min_step(int64_t v, int ctrl_sel)
+{
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+    uint32_t l2, h2;
+    switch (ctrl_sel) {
+    case 0:
+        l2 = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0xB1, 0xF, 0xF, false);
+        h2 = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0xB1, 0xF, 0xF, false);
+        break;
+    case 1:
+        l2 = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0x4E, 0xF, 0xF, false);
+        h2 = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0x4E, 0xF, 0xF, false);
+        break;
+    case 2:
+        l2 = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0x141, 0xF, 0xF, false);
+        h2 = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0x141, 0xF, 0xF, false);
+        break;
+    default:
+        l2 = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, 0x140, 0xF, 0xF, false);
+        h2 = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, 0x140, 0xF, 0xF, false);
+        break;
+    }
+    const int64_t o = (int64_t)(((uint64_t)h2 << 32) | l2);
+    return o < v ? o : v;
+}
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
+{
+    v = dpp_min_step(v, 0);
+    v = dpp_min_step(v, 1);
+    v = dpp_min_step(v, 2);
+    v = dpp_min_step(v, 3);
+    const uint64_t u = (uint64_t)v;
+    int64_t m = NONE;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 16 * r);
+        const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 16 * r);
+        const int64_t x = (int64_t)(((uint64_t)h << 32) | l);
+        m = x < m ? x : m;
+    }
+    return m;
+}
+
+// seg_next for a wave-uniform x (all lanes active), one Hamming weight per
+// lane: every w's smallest weight >= x, then their minimum.
+__device__ int64_t seg_next_wave(const Seg& g, int64_t x)
+{
+    if (x <= 0) return 0;
+    const int w = lane_id() + 1;
+    int64_t c = NONE;
+    if (w <= wcap(g)) {
+        const int64_t wJ = (int64_t)w * g.J;
+        const int64_t lo = wJ + g.B * lw_min(w);
+        if (lo >= x) {
+            c = lo;
+        } else {
+            const int lm = w * g.len - w * (w - 1) / 2;
+            const int top = lm < SL - 1 ? lm : SL - 1;
+            const int64_t hi = wJ + (int64_t)((uint32_t)g.B * (uint32_t)top);
+            if (x <= hi) {
+                uint32_t rem;
+                const uint32_t q = seg_div(g, (uint32_t)(x - lo) + (uint32_t)g.B - 1u, rem);
+                c = lo + (int64_t)q * g.B;
+            }
+        }
+    }
+    return wave_min_i64(c);
 }
 
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
@@ -164,15 +295,6 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ int64_t wave_min_i64(int64_t v)
-{
-#pragma unroll
-    for (int d = 1; d < ORBG_WAVE; d <<= 1) {
-        const int64_t o = __shfl_xor(v, d, ORBG_WAVE);
-        v = o < v ? o : v;
-    }
-    return uni64(v);
-}
 
 // A split waiting to be tested (LDS ring of ORBG_ML_QCAP entries): its partial
 // weights, partial-set sizes (saturated at 2^32 - 1, exact for product indices
@@ -182,6 +304,24 @@ struct QEntry {
     int64_t a[ORBG_ML_MSEG];
     uint32_t cnt[ORBG_ML_MSEG];
     uint32_t first, total;
+};
+
+// Weights below X0 are walked from per-block bitmaps (the walk of a block
+// rarely passes weight 255, almost never 1023): R_i, the partial weights
+// segment i can take; S_i = R_i + R_{i+1} + ... + R_{m-1} (Minkowski sums), the
+// totals of segments i..m-1 that some split reaches; rS_i, S_i reflected (bit
+// j for weight X0 - 1 - j); and the partial-set sizes of the weights below CX,
+// saturated at 2^32 - 1 (larger ones are counted when needed).  Words are
+// built as the walk's weight reaches them.
+constexpr int XW = 16;
+constexpr int X0 = 64 * XW;
+constexpr int CX = 256;
+
+struct MlMaps {
+    uint64_t R[ORBG_ML_MSEG][XW];
+    uint64_t S[ORBG_ML_MSEG][XW];
+    uint64_t rS[ORBG_ML_MSEG][XW];
+    uint32_t cnt[ORBG_ML_MSEG][CX];
 };
 
 template <int M>
@@ -199,13 +339,22 @@ struct Walk {
     const uint64_t* h;      // LDS: column of each rank
     uint16_t* win;          // LDS: the winner's ranks
     QEntry* Q;              // LDS: queued splits
+    MlMaps* mp;             // LDS: bitmaps and partial-set sizes below X0
+    int built;              // bitmap words built
     int nwin;
     bool stop, found;
+    bool dry;               // enumerate without queueing (the step past X0)
     uint32_t q;
 };
 
 // Lexicographic unranking of a w-subset of {1..len} with sum s: index u (0-based)
-// among those subsets in ascending order of (v_1, v_2, ...).  emit(v) per element.
+// among those subsets in ascending order of (v_1, v_2, ...).  emit(v) per
+// element.  Each element but the last two scans its candidates c upward: the
+// rw elements after v_k = c come from {c+1..len} with sum s - c, i.e. (shifted
+// by c) from {1..len-c} with sum s - c - rw c.
+// The last two have closed forms: the pairs from {prev+1..len} with sum s are
+// (c, s - c) for c from max(prev + 1, s - len) to floor((s - 1) / 2), one for
+// each c, and a last element alone is s.
 template <typename F>
 __device__ __forceinline__ void unrank_subset(const uint32_t* __restrict__ tbl, int len, int w, int64_t s, uint64_t u,
                                               F&& emit)
@@ -213,15 +362,22 @@ __device__ __forceinline__ void unrank_subset(const uint32_t* __restrict__ tbl, 
     int prev = 0;
     for (int k = 1; k <= w; ++k) {
         const int rw = w - k;
-        int c = prev + 1;
-        for (; c <= len; ++c) {
-            // the rw elements after v_k = c come from {c+1..len} with sum s - c,
-            // i.e. (shifted by c) from {1..len-c} with sum s - c - rw c
-            const uint64_t n = subset_count(tbl, len - c, rw, s - c - (int64_t)rw * c);
-            if (u < n) break;
-            u -= n;
+        int c;
+        if (rw == 0) {
+            c = (int)s;
+        } else if (rw == 1) {
+            const int64_t first = (int64_t)prev + 1 > s - len ? (int64_t)prev + 1 : s - len;
+            c = (int)(first + (int64_t)u);
+            u = 0;
+        } else {
+            c = prev + 1;
+            for (; c <= len; ++c) {
+                const uint64_t n = subset_count(tbl, len - c, rw, s - c - (int64_t)rw * c);
+                if (u < n) break;
+                u -= n;
+            }
+            if (c > len) c = len;         // exact counts always stop the scan before
         }
-        if (c > len) c = len;                 // exact counts always stop the scan before
         emit(c);
         s -= c;
         prev = c;
@@ -239,9 +395,15 @@ __device__ __forceinline__ void unrank_partial(const uint32_t* __restrict__ tbl,
         u -= 1;
     }
     const int wc = wcap(g);
-    for (int w = 1; w <= wc && min_weight(g, w) <= x; ++w) {
-        const int64_t wp = rel_weight(g, x, w);
-        if (wp < 0) continue;
+    SegScan sc;
+    for (int w = 1; w <= wc; ++w) {
+        sc.next(g);
+        if (sc.lo > x) break;
+        if (x > sc.hi) continue;
+        uint32_t rem;
+        const uint32_t q = seg_div(g, (uint32_t)(x - sc.lo), rem);
+        if (rem != 0) continue;
+        const int64_t wp = lw_min(w) + q;
         const uint64_t n = subset_count(tbl, g.len, w, wp);
         if (u < n) {
             unrank_subset(tbl, g.len, w, wp, u, [&](int v) { emit(g.off + v); });
@@ -288,7 +450,7 @@ __device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b)
 // that decodes early is tested before much of the order is walked) and doubles
 // to 64 per step.
 template <int M>
-__device__ void flush(Walk<M>& c, bool final)
+__device__ __forceinline__ void flush(Walk<M>& c, bool final)
 {
     const int lane = lane_id();
     wave_lds_sync();                          // queue entries written by lane 0
@@ -358,7 +520,7 @@ __device__ void flush(Walk<M>& c, bool final)
 // Queues the current split (its product cut at the budget) and tests whole
 // steps of 64 queued patterns; at the budget, tests the rest and stops.
 template <int M>
-__device__ void push_split(Walk<M>& c)
+__device__ __forceinline__ void push_split(Walk<M>& c)
 {
     uint64_t count = 1;
 #pragma unroll
@@ -397,10 +559,10 @@ __device__ void push_split(Walk<M>& c)
 // -- at the last two segments, the splits -- taken in ascending order), an
 // empty stretch skipped to segment I's next value.
 template <int I, int M>
-__device__ int64_t walk_level(Walk<M>& c, int64_t rest)
+__device__ __forceinline__ int64_t walk_level(Walk<M>& c, int64_t rest)
 {
     const int64_t need = rest + 1;
-    int64_t best = seg_next(c.seg[I], need);
+    int64_t best = seg_next_wave(c.seg[I], need);
     if constexpr (I == M - 2) {
         const int lane = lane_id();
         for (int64_t base = 0; base <= rest;) {
@@ -411,9 +573,9 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
             uint64_t n0 = 0, n1 = 0;
             int64_t cand = NONE;
             if (m0) {
-                n1 = seg_count(c.tbl, c.seg[I + 1], rest - a);
+                int64_t r;
+                seg_count_next(c.tbl, c.seg[I + 1], rest - a, n1, r);
                 if (n1 != 0) n0 = seg_count(c.tbl, c.seg[I], a);
-                const int64_t r = seg_next(c.seg[I + 1], need - a);
                 if (r != NONE) cand = a + r;
             }
             const int64_t mn = wave_min_i64(cand);
@@ -425,10 +587,10 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
                 c.cnt[I] = readlane_u64(n0, l);
                 c.a[I + 1] = rest - av;
                 c.cnt[I + 1] = readlane_u64(n1, l);
-                push_split<M>(c);
+                if (!c.dry) push_split<M>(c);
             }
             if (c.stop) return NONE;
-            base = seg_next(c.seg[I], base + ORBG_WAVE);
+            base = seg_next_wave(c.seg[I], base + ORBG_WAVE);
         }
     } else {
         // 64 candidate values of W_I per step: membership and partial-set size
@@ -446,10 +608,185 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
                 if (c.stop) return NONE;
                 if (r != NONE && av + r < best) best = av + r;
             }
-            base = seg_next(c.seg[I], base + ORBG_WAVE);
+            base = seg_next_wave(c.seg[I], base + ORBG_WAVE);
         }
     }
     return best;
+}
+
+__device__ __forceinline__ uint64_t lds_u64(const uint64_t* p) { return uniform_u64(*p); }
+__device__ __forceinline__ uint32_t lds_u32(const uint32_t* p) { return uni32(*p); }
+
+__device__ __forceinline__ uint64_t bitrev64(uint64_t v)
+{
+    return ((uint64_t)__builtin_bitreverse32((uint32_t)v) << 32) | __builtin_bitreverse32((uint32_t)(v >> 32));
+}
+
+// OR of a u64 over the wave, wave-uniform (all lanes active).
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#define ORBG_OR_STEP(ctrl)                                                                    \
+    lo |= (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, ctrl, 0xF, 0xF, false);    \
+    hi |= (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, ctrl, 0xF, 0xF, false);
+    ORBG_OR_STEP(0xB1)      // quad_perm [1,0,3,2]
+    ORBG_OR_STEP(0x4E)      // quad_perm [2,3,0,1]
+    ORBG_OR_STEP(0x141)     // row_half_mirror
+    ORBG_OR_STEP(0x140)     // row_mirror
+#undef ORBG_OR_STEP
+    const uint32_t l = __builtin_amdgcn_readlane(lo, 0) | __builtin_amdgcn_readlane(lo, 16) |
+                       __builtin_amdgcn_readlane(lo, 32) | __builtin_amdgcn_readlane(lo, 48);
+    const uint32_t h = __builtin_amdgcn_readlane(hi, 0) | __builtin_amdgcn_readlane(hi, 16) |
+                       __builtin_amdgcn_readlane(hi, 32) | __builtin_amdgcn_readlane(hi, 48);
+    return ((uint64_t)h << 32) | l;
+}
+
+// seg_count for a wave-uniform x (all lanes active), one Hamming weight per
+// lane, saturated at 2^32 - 1.
+__device__ uint32_t seg_count_wave(const uint32_t* __restrict__ tbl, const Seg& g, int64_t x)
+{
+    const int w = lane_id() + 1;
+    uint64_t t = 0;
+    if (w <= wcap(g)) {
+        const int64_t wJ = (int64_t)w * g.J;
+        const int64_t lo = wJ + g.B * lw_min(w);
+        const int lm = w * g.len - w * (w - 1) / 2;
+        const int top = lm < SL - 1 ? lm : SL - 1;
+        const int64_t hi = wJ + (int64_t)((uint32_t)g.B * (uint32_t)top);
+        if (lo <= x && x <= hi) {
+            uint32_t rem;
+            const uint32_t q = seg_div(g, (uint32_t)(x - lo), rem);
+            if (rem == 0) t = subset_count(tbl, g.len, w, lw_min(w) + q);
+        }
+    }
+    uint32_t lo = (uint32_t)t, hi = (uint32_t)(t >> 32);
+#define ORBG_ADD_STEP(ctrl)                                                                          \
+    {                                                                                                \
+        const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp((int)lo, (int)lo, ctrl, 0xF, 0xF, false); \
+        const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)hi, ctrl, 0xF, 0xF, false); \
+        const uint64_t v = (((uint64_t)hi << 32) | lo) + (((uint64_t)h2 << 32) | l2);                  \
+        lo = (uint32_t)v;                                                                            \
+        hi = (uint32_t)(v >> 32);                                                                    \
+    }
+    // every lane ends with the sum over its 16-lane row (each step pairs lanes
+    // holding sums over disjoint sets)
+    ORBG_ADD_STEP(0xB1)      // quad_perm [1,0,3,2]
+    ORBG_ADD_STEP(0x4E)      // quad_perm [2,3,0,1]
+    ORBG_ADD_STEP(0x141)     // row_half_mirror
+    ORBG_ADD_STEP(0x140)     // row_mirror
+#undef ORBG_ADD_STEP
+    uint64_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        sum += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, 16 * r) << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)lo, 16 * r);
+    if (x == 0) sum += 1;
+    return sum > 0xffffffffull ? 0xffffffffu : (uint32_t)sum;
+}
+
+// Partial-set size of weight x < X0 of segment i: the cached one below CX.
+template <int M>
+__device__ __forceinline__ uint32_t map_count(Walk<M>& c, int i, int x)
+{
+    if (x < CX) return lds_u32(&c.mp->cnt[i][x]);
+    return seg_count_wave(c.tbl, c.seg[i], x);
+}
+
+// Builds word k of every map (weights 64k .. 64k + 63): partial-set sizes and
+// R_i, one weight per lane; then S_i from the last segment back: word k of
+// S_i is the OR over a in R_i (a < 64 (k + 1)) of word k of S_{i+1} shifted
+// up by a, 64 values of a per pass (lane l: a = 64 p + l, shift l of words
+// k - p and k - p - 1); rS_i gets the word reflected.
+template <int M>
+__device__ __forceinline__ void build_word(Walk<M>& c, int k)
+{
+    const int lane = lane_id();
+    MlMaps& mp = *c.mp;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int x = 64 * k + lane;
+        bool mem;
+        if (x < CX) {
+            const uint64_t n = seg_count(c.tbl, c.seg[i], x);
+            mp.cnt[i][x] = n > 0xffffffffull ? 0xffffffffu : (uint32_t)n;
+            mem = n != 0;
+        } else {
+            mem = seg_member(c.seg[i], x);
+        }
+        const uint64_t r = ballot(mem);
+        if (lane == 0) mp.R[i][k] = r;
+        if (i == M - 1 && lane == 0) {
+            mp.S[i][k] = r;
+            mp.rS[i][XW - 1 - k] = bitrev64(r);
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = M - 2; i >= 0; --i) {
+        uint64_t acc = 0;
+        for (int p = 0; p <= k; ++p) {
+            const uint64_t member = lds_u64(&mp.R[i][p]);
+            const uint64_t hi = lds_u64(&mp.S[i + 1][k - p]);
+            const uint64_t lo = k - p - 1 >= 0 ? lds_u64(&mp.S[i + 1][k - p - 1]) : 0ull;
+            const uint64_t w = lane == 0 ? hi : (hi << lane) | (lo >> (64 - lane));
+            acc |= ((member >> lane) & 1ull) ? w : 0ull;
+        }
+        const uint64_t sk = wave_or_u64(acc);
+        if (lane == 0) {
+            mp.S[i][k] = sk;
+            mp.rS[i][XW - 1 - k] = bitrev64(sk);
+        }
+        wave_lds_sync();
+    }
+}
+
+// Queues every split of `rest` (< 64 built words) over segments I..M-1 in the
+// nested-loop order: the values a <= rest of R_I with rest - a in S_{I+1}, as
+// the AND of R_I with rS_{I+1} shifted down by X0 - 1 - rest (bit a of the
+// shifted map is bit rest - a of S_{I+1}; a > rest falls past the map).
+template <int I, int M>
+__device__ __forceinline__ void enum_splits(Walk<M>& c, int rest)
+{
+    MlMaps& mp = *c.mp;
+    const int d = X0 - 1 - rest, q = d >> 6, r = d & 63;
+    for (int j = 0; j <= (rest >> 6); ++j) {
+        const uint64_t lo = j + q < XW ? lds_u64(&mp.rS[I + 1][j + q]) : 0ull;
+        const uint64_t hi = j + q + 1 < XW ? lds_u64(&mp.rS[I + 1][j + q + 1]) : 0ull;
+        const uint64_t sh = r == 0 ? lo : (lo >> r) | (hi << (64 - r));
+        uint64_t bits = lds_u64(&mp.R[I][j]) & sh;
+        while (bits != 0) {
+            const int a = 64 * j + __builtin_ctzll(bits);
+            bits &= bits - 1;
+            c.a[I] = a;
+            c.cnt[I] = map_count(c, I, a);
+            if constexpr (I == M - 2) {
+                c.a[I + 1] = rest - a;
+                c.cnt[I + 1] = map_count(c, I + 1, rest - a);
+                push_split<M>(c);
+            } else {
+                enum_splits<I + 1, M>(c, rest - a);
+            }
+            if (c.stop) return;
+        }
+    }
+}
+
+// Smallest total weight above W from S_0, building words as needed; -1 when
+// there is none below X0.
+template <int M>
+__device__ __forceinline__ int64_t next_total_map(Walk<M>& c, int64_t W)
+{
+    for (int64_t t = W + 1; t < X0;) {
+        const int k = (int)(t >> 6);
+        if (k >= c.built) {
+            build_word<M>(c, k);
+            c.built = k + 1;
+        }
+        const uint64_t bits = lds_u64(&c.mp->S[0][k]) & (~0ull << (t & 63));
+        if (bits != 0) return 64 * k + __builtin_ctzll(bits);
+        t = 64 * (int64_t)(k + 1);
+    }
+    return -1;
 }
 
 // Reliability weights in increasing order, each one's splits queued and tested.
@@ -457,11 +794,47 @@ __device__ int64_t walk_level(Walk<M>& c, int64_t rest)
 // limit is at most 2^n, and the restricted order holds min(2^n, the budget)
 // patterns at least), so the queue has been tested by then.
 template <int M>
-__device__ void walk(Walk<M>& c)
+__device__ __forceinline__ void walk(Walk<M>& c)
 {
+    // weights below X0 from the maps
+    {
+        MlMaps& mp = *c.mp;
+        const int lane = lane_id();
+        uint64_t* words = &mp.R[0][0];
+        for (int i = lane; i < 3 * ORBG_ML_MSEG * XW; i += ORBG_WAVE) words[i] = 0ull;
+        wave_lds_sync();
+        build_word<M>(c, 0);
+        c.built = 1;
+    }
     int64_t W = 0;
     for (;;) {
-        int64_t nxt;
+        if constexpr (M == 1) {
+            if ((lds_u64(&c.mp->R[0][W >> 6]) >> (W & 63)) & 1ull) {
+                c.a[0] = W;
+                c.cnt[0] = map_count(c, 0, (int)W);
+                push_split<1>(c);
+            }
+        } else {
+            enum_splits<0, M>(c, (int)W);
+        }
+        if (c.stop) return;
+        const int64_t nx = next_total_map<M>(c, W);
+        if (nx < 0) break;
+        W = nx;
+    }
+    // the first weight at or above X0: one pass over the splits of X0 - 1
+    // without queueing them (they were queued from the maps)
+    int64_t nxt;
+    if constexpr (M == 1) {
+        nxt = seg_next_wave(c.seg[0], X0);
+    } else {
+        c.dry = true;
+        nxt = walk_level<0, M>(c, X0 - 1);
+        c.dry = false;
+    }
+    if (nxt == NONE) return;
+    W = uni64(nxt);
+    for (;;) {
         if constexpr (M == 1) {
             const uint64_t n = seg_count(c.tbl, c.seg[0], W);
             if (n != 0) {
@@ -469,7 +842,7 @@ __device__ void walk(Walk<M>& c)
                 c.cnt[0] = n;
                 push_split<1>(c);
             }
-            nxt = seg_next(c.seg[0], W + 1);
+            nxt = seg_next_wave(c.seg[0], W + 1);
         } else {
             nxt = walk_level<0, M>(c, W);
         }
@@ -496,6 +869,7 @@ struct MlLds {
     int anc[ORBG_ML_MSEG + 2];          // anchor ranks, ascending
     uint16_t win[ORBG_ML_WINCAP + 1];   // winner's ranks, then their count
     QEntry Q[ORBG_ML_QCAP];             // splits waiting to be tested
+    MlMaps maps;                        // bitmaps of the walk below weight X0
 };
 
 struct Model {
@@ -517,7 +891,7 @@ __device__ __forceinline__ void model_basic(Model& md, int n)
 // Fit with at most mreq segments (L in LDS, ranks 1..n; h = n/2 <= 32 NK).
 // Wave-uniform result.
 template <int NK, typename Lds>
-__device__ Model fit_model(Lds& S, int n, int mreq, bool jdiv)
+__device__ __forceinline__ Model fit_model(Lds& S, int n, int mreq, bool jdiv)
 {
     const int lane = lane_id();
     Model md;
@@ -619,7 +993,7 @@ __device__ Model fit_model(Lds& S, int n, int mreq, bool jdiv)
 }
 
 template <int M, typename Lds>
-__device__ void decode_walk(const Model& md, const uint32_t* tbl, Lds& S, uint64_t s0, uint32_t limit,
+__device__ __forceinline__ void decode_walk(const Model& md, const uint32_t* tbl, Lds& S, uint64_t s0, uint32_t limit,
                             bool& found, uint32_t& q, int& nwin)
 {
     Walk<M> c;
@@ -629,6 +1003,7 @@ __device__ void decode_walk(const Model& md, const uint32_t* tbl, Lds& S, uint64
         c.seg[i].B = md.B[i];
         c.seg[i].off = md.I[i];
         c.seg[i].len = md.I[i + 1] - md.I[i];
+        c.seg[i].rcp = 0xffffffffu / (uint32_t)md.B[i];
     }
     c.qbase = 0;
     c.pending = 0;
@@ -641,6 +1016,9 @@ __device__ void decode_walk(const Model& md, const uint32_t* tbl, Lds& S, uint64
     c.tbl = tbl;
     c.h = S.h;
     c.win = S.win;
+    c.mp = &S.maps;
+    c.built = 0;
+    c.dry = false;
     c.nwin = 0;
     c.stop = false;
     c.found = false;
