@@ -328,7 +328,7 @@ template <int M>
 struct Walk {
     Seg seg[M];
     int64_t a[M];           // current split
-    uint64_t cnt[M];        // partial-set sizes of the split
+    uint32_t cnt[M];        // partial-set sizes of the split, saturated at 2^32 - 1
     uint64_t qbase;         // patterns tested
     uint32_t pending;       // patterns queued, not yet tested
     uint32_t want;          // queued patterns that start a test: 2, doubling to 64
@@ -435,13 +435,7 @@ __device__ __forceinline__ void unrank_product(const Seg (&seg)[M], const uint32
     for (int i = 0; i < M; ++i) unrank_partial(tbl, seg[i], a[i], t[i], emit);
 }
 
-__device__ __forceinline__ uint64_t sat_mul(uint64_t a, uint64_t b)
-{
-    const uint64_t cap = 1ull << 40;
-    if (a == 0 || b == 0) return 0;
-    if (a >= cap || b >= cap || a > cap / b) return cap;
-    return a * b;
-}
+__device__ __forceinline__ uint32_t sat32(uint64_t v) { return v < 0xffffffffull ? (uint32_t)v : 0xffffffffu; }
 
 // Tests queued patterns up to 64 at a time in queue order while at least
 // `want` are queued (all of them when `final`): lane l takes the l-th untested
@@ -522,9 +516,14 @@ __device__ __forceinline__ void flush(Walk<M>& c, bool final)
 template <int M>
 __device__ __forceinline__ void push_split(Walk<M>& c)
 {
+    // product of the partial-set sizes (each below 2^32), capped at 2^32, which
+    // is above any budget
     uint64_t count = 1;
 #pragma unroll
-    for (int i = 0; i < M; ++i) count = sat_mul(count, c.cnt[i]);
+    for (int i = 0; i < M; ++i) {
+        count *= c.cnt[i];
+        count = count < (1ull << 32) ? count : (1ull << 32);
+    }
     const uint64_t room = (uint64_t)c.budget - c.qbase - c.pending;        // > 0 while the walk runs
     const uint32_t tot = (uint32_t)(count < room ? count : room);
     const int slot = (c.qhead + c.live) % ORBG_ML_QCAP;                     // live < 64 here
@@ -533,8 +532,7 @@ __device__ __forceinline__ void push_split(Walk<M>& c)
 #pragma unroll
         for (int i = 0; i < ORBG_ML_MSEG; ++i) {
             q.a[i] = i < M ? c.a[i < M ? i : 0] : 0;
-            q.cnt[i] = i < M ? (uint32_t)(c.cnt[i < M ? i : 0] > 0xffffffffull ? 0xffffffffull : c.cnt[i < M ? i : 0])
-                             : 1u;
+            q.cnt[i] = i < M ? c.cnt[i < M ? i : 0] : 1u;
         }
         q.first = 0;
         q.total = tot;
@@ -584,9 +582,9 @@ __device__ __forceinline__ int64_t walk_level(Walk<M>& c, int64_t rest)
                 const int l = __builtin_ctzll(bal);
                 const int64_t av = base + (int64_t)l;
                 c.a[I] = av;
-                c.cnt[I] = readlane_u64(n0, l);
+                c.cnt[I] = sat32(readlane_u64(n0, l));
                 c.a[I + 1] = rest - av;
-                c.cnt[I + 1] = readlane_u64(n1, l);
+                c.cnt[I + 1] = sat32(readlane_u64(n1, l));
                 if (!c.dry) push_split<M>(c);
             }
             if (c.stop) return NONE;
@@ -603,7 +601,7 @@ __device__ __forceinline__ int64_t walk_level(Walk<M>& c, int64_t rest)
                 const int l = __builtin_ctzll(bal);
                 const int64_t av = base + (int64_t)l;
                 c.a[I] = av;
-                c.cnt[I] = readlane_u64(n0, l);
+                c.cnt[I] = sat32(readlane_u64(n0, l));
                 const int64_t r = walk_level<I + 1, M>(c, rest - av);
                 if (c.stop) return NONE;
                 if (r != NONE && av + r < best) best = av + r;
@@ -839,7 +837,7 @@ __device__ __forceinline__ void walk(Walk<M>& c)
             const uint64_t n = seg_count(c.tbl, c.seg[0], W);
             if (n != 0) {
                 c.a[0] = W;
-                c.cnt[0] = n;
+                c.cnt[0] = sat32(n);
                 push_split<1>(c);
             }
             nxt = seg_next_wave(c.seg[0], W + 1);
