@@ -57,7 +57,8 @@ def test_mixed_matches_oracle(gpu_device):
 @pytest.mark.parametrize("params", [
     dict(split_steps=0), dict(split_steps=1), dict(split_steps=3, heavy_waves=4),
     dict(split_steps=64, heavy_waves=16, heavy_workgroups_per_cu=1), dict(workgroups_per_cu=1, chunk=7),
-    dict(workgroups_per_cu=64, chunk=1, split_steps=8, heavy_waves=8, heavy_workgroups_per_cu=16)])
+    dict(workgroups_per_cu=64, chunk=1, split_steps=8, heavy_waves=8, heavy_workgroups_per_cu=16),
+    dict(one_block_per_workgroup=1)])
 def test_schedule_invariance(gpu_device, params):
     """Any launch shape gives the same bits as the plain per-code decode."""
     print(f"invariance {params}", flush=True)
@@ -88,6 +89,24 @@ def test_single_code_split_invariance(gpu_device, split, waves):
     for a, b in zip(ref, got):
         assert (a == b).all()
     sample = np.arange(0, 20000, 40)
+    ocw, oq, oab = O.decode(H, llr[sample], 10 ** 5, THREADS)
+    assert (got[0][sample] == ocw).all() and (got[1][sample].astype(np.uint64) == oq).all()
+
+
+def test_single_code_naive_launch(gpu_device):
+    """One one-wave workgroup per block (no work counter, no split): the same bits
+    as the persistent launch, and the oracle's on a sample."""
+    print("single naive launch", flush=True)
+    H, G = codes.code("bch127_113")
+    from synth import channel
+    llr, _ = channel.awgn_llr(G, 20000, 4.5, seed=78)
+    x = torch.from_numpy(llr).to(gpu_device)
+    ref = [v.cpu().numpy() for v in binding.orbg_decode_ex(H, x, 10 ** 5)]
+    got = [v.cpu().numpy() for v in binding.orbg_decode_ex(
+        H, x, 10 ** 5, params=binding.LaunchParams(one_block_per_workgroup=1))]
+    for a, b in zip(ref, got):
+        assert (a == b).all()
+    sample = np.arange(0, 20000, 50)
     ocw, oq, oab = O.decode(H, llr[sample], 10 ** 5, THREADS)
     assert (got[0][sample] == ocw).all() and (got[1][sample].astype(np.uint64) == oq).all()
 
