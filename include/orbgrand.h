@@ -143,10 +143,17 @@ int orbg_decode_ex(const uint8_t* H, const float* llr, int n, int k, uint64_t bu
  * there on every J0 tests the same first `budget` patterns in the same order,
  * so larger fitted offsets decode with the schedule of j0max.  That takes
  * (j0max + 2) x 8 x budget bytes of device memory (about 0.2 GB for n = 127,
- * budget 10^5).  Returns ORBG_EINVAL when those patterns reach a logistic
- * weight above 255, or flip more than 7 ranks above 8 at logistic weight 100
- * or more (e.g. n = 256 with a budget above 256, n = 127 with a budget above
- * about 2.86 x 10^5).
+ * budget 10^5).  The schedules cannot hold orders whose first `budget`
+ * patterns reach a logistic weight above 255 or flip more than 7 ranks above 8
+ * at logistic weight 100 or more (e.g. n = 256 with a budget above 256,
+ * n = 127 with a budget above about 2.86 x 10^5), nor budgets above 2^22.  Such
+ * a decode (n <= 512) runs on the full m-line kernel with one segment, whose
+ * fit and order are exactly the above (orbg_decode_mline with segments = 1 and
+ * jdiv = 0, plus the J0 output); `params` is then unused, and the first such
+ * call on a device builds the m-line decoder's table (see orbg_decode_mline).
+ * Budget: 1 .. 5 x 10^6.  Errors: ORBG_EINVAL for arguments outside these
+ * limits (n > 512 with an order the schedules cannot hold), as orbg_decode
+ * otherwise.
  */
 int orbg_decode_1line(const uint8_t* H, const float* llr, int n, int k, uint64_t budget,
                       int64_t batch, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -60,6 +61,8 @@ std::vector<CodeEntry*> g_registry;
 std::map<std::tuple<int, int, uint64_t>, orbg::Schedule*> g_sched;
 // (device, n, len) -> 1-line schedules
 std::map<std::tuple<int, int, uint64_t>, orbg::Schedule1*> g_sched1;
+// (device, n, length) whose 1-line order the per-offset schedules cannot hold
+std::set<std::tuple<int, int, uint64_t>> g_sched1_no;
 // (device, stream) -> work space
 std::map<std::pair<int, hipStream_t>, Workspace> g_work;
 // device -> compute units
@@ -182,11 +185,15 @@ int get_schedule_1line(int n, uint64_t need, hipStream_t stream, const orbg::Sch
     auto key = std::make_tuple(dev, n, len);
     auto it = g_sched1.find(key);
     if (it != g_sched1.end()) { *out = it->second; return ORBG_OK; }
+    if (g_sched1_no.count(key))
+        return fail(ORBG_EINVAL, "1-line schedule: the order of %llu patterns at n = %d does not fit the schedules",
+                    (unsigned long long)len, n);
     orbg::Schedule1* s = new orbg::Schedule1;
     char err[256] = {0};
     const int rc = orbg_build_schedule_1line(n, len, stream, s, err, sizeof(err));
     if (rc != 0) {
         delete s;
+        if (rc == -1) g_sched1_no.insert(key);
         return fail(rc == -2 ? ORBG_ENOMEM : (rc == -1 ? ORBG_EINVAL : ORBG_EHIP), "%s", err);
     }
     g_sched1[key] = s;
@@ -390,6 +397,46 @@ int compute_units(int dev, int* cus)
     return ORBG_OK;
 }
 
+// Full m-line decode of a checked request (n <= ORBG_ML_LMAX, budget <=
+// ORBG_ML_BUDGET_MAX, segments and jdiv in range).  j0: per-block J_0 of the
+// fit, or NULL.
+int decode_mline_checked(const CodeEntry* code, const float* llr, uint64_t budget, int64_t batch, int segments,
+                         int jdiv, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned, int32_t* segments_out,
+                         int32_t* j0, hipStream_t st)
+{
+    int rc;
+    const uint32_t* tbl = nullptr;
+    if ((rc = get_ml_table(st, &tbl))) return rc;
+    if (batch == 0) return ORBG_OK;
+    Workspace* w = nullptr;
+    int cus = 0;
+    if ((rc = get_workspace(st, 0, &w, &cus))) return rc;
+    orbg::MlineArgs a;
+    a.llr = llr;
+    a.n = code->n;
+    a.m = code->n - code->k;
+    a.cols = code->d_cols;
+    a.rows = code->d_rows;
+    a.nblocks = batch;
+    a.budget = (uint32_t)budget;
+    a.mseg = segments;
+    a.jdiv = jdiv != 0;
+    a.table = tbl;
+    a.cw = codeword;
+    a.queries = queries;
+    a.abandoned = abandoned;
+    a.mfit = segments_out;
+    a.j0 = j0;
+    // one-wave workgroups, several times more than fit at once: each takes a
+    // strided share of the blocks, and the hardware hands out the later
+    // workgroups as earlier ones finish, which evens out blocks of unequal cost
+    // (measured: 96 per CU decodes the 4 dB BCH point 1.2x faster than 32)
+    const int64_t grid = std::min<int64_t>(batch, (int64_t)cus * 96);
+    const hipError_t e = orbg::launch_mline(a, (int)grid, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "m-line decode launch failed: %s", hipGetErrorString(e));
+    return ORBG_OK;
+}
+
 int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t budget, int64_t batch,
                   const uint8_t* order, uint8_t* codeword, uint64_t* queries, uint8_t* abandoned,
                   const orbg_launch_params* params, void* stream, bool oneline = false, int32_t* j0 = nullptr)
@@ -400,16 +447,28 @@ int decode_single(const uint8_t* H, const float* llr, int n, int k, uint64_t bud
     if (batch > 0 && (!llr || !codeword || !queries || !abandoned))
         return fail(ORBG_EINVAL, "a device buffer is NULL");
     if (order && n < 12) return fail(ORBG_EINVAL, "a batch order needs n >= 12 (got %d)", n);
-    if (oneline && budget > ORBG_BUDGET_MAX_1LINE)
-        return fail(ORBG_EINVAL, "budget = %llu outside [1, 2^22] for the 1-line order", (unsigned long long)budget);
+    if (oneline && budget > ORBG_BUDGET_MAX_1LINE && n > ORBG_ML_LMAX)
+        return fail(ORBG_EINVAL, "budget = %llu above 2^22, the 1-line schedules' limit, and n = %d above %d for "
+                    "the one-segment m-line decode", (unsigned long long)budget, n, ORBG_ML_LMAX);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CodeEntry* code = nullptr;
     if ((rc = get_code(H, n, k, &code))) return rc;
     orbg::DecodeArgs a;
     std::memset(&a, 0, sizeof(a));
     a.codes.ncodes = 1;
-    if (oneline) rc = describe_1line(code, budget, st, &a.codes.c[0]);
-    else rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]);
+    if (oneline) {
+        // 1-line ORBGRAND is full ORBGRAND with one segment (the same fit and
+        // order): where the per-offset schedules cannot hold the order of
+        // (n, budget), the m-line kernel decodes with one segment
+        rc = budget <= ORBG_BUDGET_MAX_1LINE ? describe_1line(code, budget, st, &a.codes.c[0]) : ORBG_EINVAL;
+        if (rc == ORBG_EINVAL && n <= ORBG_ML_LMAX) {
+            g_err.clear();
+            return decode_mline_checked(code, llr, budget, batch, 1, 0, codeword, queries, abandoned, nullptr, j0,
+                                        st);
+        }
+    } else {
+        rc = describe(code, order && budget < 4096 ? 4096 : budget, st, 0, &a.codes.c[0]);
+    }
     if (rc) return rc;
     a.codes.rwords = a.codes.c[0].m * a.codes.c[0].nk;
     if (batch == 0) return ORBG_OK;
@@ -567,35 +626,8 @@ int orbg_decode_mline(const uint8_t* H, const float* llr, int n, int k, uint64_t
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     CodeEntry* code = nullptr;
     if ((rc = get_code(H, n, k, &code))) return rc;
-    const uint32_t* tbl = nullptr;
-    if ((rc = get_ml_table(st, &tbl))) return rc;
-    if (batch == 0) return ORBG_OK;
-    Workspace* w = nullptr;
-    int cus = 0;
-    if ((rc = get_workspace(st, 0, &w, &cus))) return rc;
-    orbg::MlineArgs a;
-    a.llr = llr;
-    a.n = n;
-    a.m = n - k;
-    a.cols = code->d_cols;
-    a.rows = code->d_rows;
-    a.nblocks = batch;
-    a.budget = (uint32_t)budget;
-    a.mseg = segments;
-    a.jdiv = jdiv != 0;
-    a.table = tbl;
-    a.cw = codeword;
-    a.queries = queries;
-    a.abandoned = abandoned;
-    a.mfit = segments_out;
-    // one-wave workgroups, several times more than fit at once: each takes a
-    // strided share of the blocks, and the hardware hands out the later
-    // workgroups as earlier ones finish, which evens out blocks of unequal cost
-    // (measured: 96 per CU decodes the 4 dB BCH point 1.2x faster than 32)
-    const int64_t grid = std::min<int64_t>(batch, (int64_t)cus * 96);
-    const hipError_t e = orbg::launch_mline(a, (int)grid, st);
-    if (e != hipSuccess) return fail(ORBG_EHIP, "m-line decode launch failed: %s", hipGetErrorString(e));
-    return ORBG_OK;
+    return decode_mline_checked(code, llr, budget, batch, segments, jdiv, codeword, queries, abandoned, segments_out,
+                                nullptr, st);
 }
 
 int orbg_code_register(const uint8_t* H, int n, int k, int* code_id)

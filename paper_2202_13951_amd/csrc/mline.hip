@@ -1058,7 +1058,8 @@ __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(
         uint32_t q = a.budget;
         int nwin = 0;
         int m_used = 1;
-        if (s0 != 0 || a.mfit != nullptr) {
+        int32_t j0v = 0;
+        if (s0 != 0 || a.mfit != nullptr || a.j0 != nullptr) {
             // full reliability order, exact keys
             uint64_t key[NK];
 #pragma unroll
@@ -1080,6 +1081,7 @@ __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(
             wave_lds_sync();
             const Model md = fit_model<NK>(S, n, a.mseg, a.jdiv);
             m_used = md.m;
+            j0v = (int32_t)md.J[0];
             // queries to make: the budget, at most all 2^n patterns (they hold
             // a member, so the walk ends at a hit before running out)
             const uint32_t limit = (n < 32 && a.budget > (1u << n)) ? (1u << n) : a.budget;
@@ -1120,6 +1122,7 @@ __global__ void __launch_bounds__(ORBG_WAVE) __attribute__((amdgpu_waves_per_eu(
             a.queries[b] = found ? (uint64_t)q : (uint64_t)a.budget;
             a.abandoned[b] = found ? 0 : 1;
             if (a.mfit != nullptr) a.mfit[b] = m_used;
+            if (a.j0 != nullptr) a.j0[b] = j0v;
         }
         wave_lds_sync();
     }

@@ -28,6 +28,7 @@ struct MlineArgs {
     uint64_t* queries;
     uint8_t* abandoned;
     int32_t* mfit;             // per-block segment count, or nullptr
+    int32_t* j0;               // per-block J_0 of the fit (the 1-line offset for one segment), or nullptr
 };
 
 // Entries of the subset-count table: (LMAX + 1) x (WMAX + 1) x SMAX.

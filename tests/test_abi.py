@@ -135,7 +135,8 @@ def test_binding_decode_rejects_bad_tensors(case, msg):
     (0, 0, 10, True, "n = 0"),
     (100, 30, 10, True, "n - k = 70"),
     (32, 26, 0, True, "budget = 0"),
-    (32, 26, (1 << 22) + 1, True, "budget"),
+    (32, 26, 5 * 10 ** 6 + 1, True, "budget = 5000001"),
+    (600, 590, (1 << 22) + 1, True, "above 2^22"),
     (32, 26, 100, False, "device buffer is NULL"),
 ])
 def test_1line_argument_errors(n, k, budget, bufs, msg):

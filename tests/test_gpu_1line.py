@@ -160,10 +160,27 @@ def test_empty_batch_and_unsupported(gpu_device):
     cw, q, ab, j0 = binding.orbg_decode_1line(H, llr, 100)
     torch.cuda.synchronize()
     assert cw.shape == (0, 32) and j0.shape == (0,)
-    H256, _ = codes.code("rlc256_240")
-    llr = torch.zeros((4, 256), dtype=torch.float32, device=gpu_device)
-    with pytest.raises(binding.OrbgError):                    # singles beyond logistic weight 255
-        binding.orbg_decode_1line(H256, llr, 1000)
+    H600 = codes.rlc_H(600, 590, seed=3)
+    llr = torch.zeros((4, 600), dtype=torch.float32, device=gpu_device)
+    with pytest.raises(binding.OrbgError):                    # past the schedules and past n = 512
+        binding.orbg_decode_1line(H600, llr, (1 << 22) + 1)
+
+
+@pytest.mark.parametrize("name,ebn0,budget,N", [("rlc256_234", 5.0, 10 ** 5, 300), ("rlc256_240", 4.0, 1000, 400),
+                                                ("bch127_113", 3.5, 4 * 10 ** 5, 200),
+                                                ("rlc64_52", 2.0, 5 * 10 ** 6, 40)])
+def test_beyond_the_schedules(gpu_device, name, ebn0, budget, N):
+    """Orders the per-offset schedules cannot hold (n = 256 past a budget of 256,
+    BCH(127,113) past about 2.86 x 10^5, any budget past 2^22) decode on the
+    one-segment m-line kernel: codeword, queries, abandon flag and J0 against
+    the oracle's 1-line decoder."""
+    print(f"1-line beyond the schedules {name} budget={budget}", flush=True)
+    H, G = codes.code(name)
+    llr, _ = channel.awgn_llr(G, N, ebn0, seed=2561)
+    want = O.decode_1line(H, llr, budget, THREADS)
+    _assert_same(_gpu(H, llr, budget, gpu_device), want, name)
+    _assert_same(_gpu(H, llr, budget, gpu_device, j0=None), want, name + " no j0", check_j0=False)
+    assert (want[1] > 256).any()
 
 
 def test_bch_full_size_sampled(gpu_device):
