@@ -55,9 +55,16 @@ int main()
     lp.one_block_per_workgroup = 2;
     EXPECT(orbg_decode_ex(H.data(), (float*)p, 32, 26, 100, 4, nullptr, u8, (uint64_t*)p, u8, &lp, nullptr),
            ORBG_EINVAL, "one_block_per_workgroup");
-    EXPECT(orbg_decode_1line(H.data(), (float*)p, 32, 26, (1u << 22) + 1, 4, u8, (uint64_t*)p, u8, nullptr, nullptr,
+    EXPECT(orbg_decode_1line(H.data(), (float*)p, 32, 26, 5000001, 4, u8, (uint64_t*)p, u8, nullptr, nullptr,
                              nullptr),
            ORBG_EINVAL, "budget");
+    {
+        // past the 1-line schedules' budget limit and past the m-line kernel's length
+        std::vector<uint8_t> H600(10 * 600, 0);
+        EXPECT(orbg_decode_1line(H600.data(), (float*)p, 600, 590, (1u << 22) + 1, 4, u8, (uint64_t*)p, u8, nullptr,
+                                 nullptr, nullptr),
+               ORBG_EINVAL, "above 2^22");
+    }
     EXPECT(orbg_decode_mline(H.data(), (float*)p, 32, 26, 100, 4, 5, 0, u8, (uint64_t*)p, u8, nullptr, nullptr),
            ORBG_EINVAL, "segments");
     EXPECT(orbg_decode_mline(H.data(), (float*)p, 32, 26, 100, 4, 2, 2, u8, (uint64_t*)p, u8, nullptr, nullptr),
