@@ -313,6 +313,18 @@ int orbg_mlp_adam(float* w, float* m, float* v, const float* grads, float lr, in
  * [batch x 64] u8. */
 int orbg_mlp_order(const float* logits, int64_t batch, uint8_t* order, void* stream);
 
+/* Fused inference without a work space: features (from DEVICE llr rows of
+ * length 128 -- row ids[b] for output row b when ids is not NULL, else row b;
+ * a row outside [0, llr_rows) gives zero features -- as orbg_mlp_features; or
+ * the given BF16 features x when llr is NULL), the three layers with the
+ * activations kept on chip, then logits [batch x 64] FP32 (or NULL) and/or the
+ * batch order [batch x 64] u8 (or NULL) as orbg_mlp_order, with batch 0 first
+ * whatever its logit when pin0 = 1.  The logits equal orbg_mlp_forward's bit
+ * for bit.  0 <= batch < 2^36.  Errors: ORBG_EINVAL for a NULL input, both
+ * outputs NULL or a negative llr_rows. */
+int orbg_mlp_infer(const float* w, const uint16_t* wb, const float* llr, int64_t llr_rows, const int64_t* ids,
+                   const uint16_t* x, int64_t batch, float* logits, uint8_t* order, int pin0, void* stream);
+
 /*
  * Learned proposal in gated form: the network runs only for blocks the plain
  * order's first batch does not decide.

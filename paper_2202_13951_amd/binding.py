@@ -79,6 +79,8 @@ def load():
     L.orbg_mlp_adam.restype = ci
     L.orbg_mlp_order.argtypes = [vp, i64, vp, vp]
     L.orbg_mlp_order.restype = ci
+    L.orbg_mlp_infer.argtypes = [vp, vp, vp, i64, vp, vp, i64, vp, vp, ci, vp]
+    L.orbg_mlp_infer.restype = ci
     L.orbg_schedule_export.argtypes = [ci, u64, vp, vp]
     L.orbg_schedule_export.restype = ci
     L.orbg_decode_1line.argtypes = [vp, vp, ci, ci, u64, i64, vp, vp, vp, vp, vp, vp]
@@ -400,6 +402,34 @@ def orbg_mlp_adam(w, m, v, grads, lr: float, step: int, wb, wt, stream=None):
 
 def orbg_mlp_order(logits, order, stream=None):
     _check("orbg_mlp_order", load().orbg_mlp_order(_p(logits), logits.shape[0], _p(order), _stream_ptr(stream)))
+
+
+def orbg_mlp_infer(w, wb, llr=None, ids=None, x=None, logits=None, order=None, pin0: bool = False, stream=None):
+    """Fused inference: features of llr rows (row ids[b], or b) or the given
+    features x, the three layers, then logits [N, 64] f32 and/or the batch order
+    [N, 64] u8 (pass the output tensors to fill)."""
+    import torch
+    if (llr is None) == (x is None):
+        raise ValueError("orbg_mlp_infer takes exactly one of llr and x")
+    rows = 0
+    if llr is not None:
+        rows = _llr_rows(llr, 128)
+        N = rows if ids is None else int(ids.numel())
+        dev = llr.device
+        if ids is not None:
+            _dev_tensor(ids, "ids", torch.int64, (N,), dev)
+    else:
+        _dev_tensor(x, "x", torch.int16, (x.shape[0], 128), x.device)
+        N, dev = x.shape[0], x.device
+    if logits is None and order is None:
+        raise ValueError("orbg_mlp_infer needs logits or order")
+    if logits is not None:
+        _dev_tensor(logits, "logits", torch.float32, (N, 64), dev)
+    if order is not None:
+        _dev_tensor(order, "order", torch.uint8, (N, 64), dev)
+    _check("orbg_mlp_infer", load().orbg_mlp_infer(_p(w), _p(wb), _p(llr), rows, _p(ids), _p(x), N, _p(logits),
+                                                   _p(order), int(bool(pin0)), _stream_ptr(stream)))
+    return logits, order
 
 
 def orbg_learned_workspace_bytes(batch: int) -> int:

@@ -729,8 +729,6 @@ int orbg_schedule_export_1line(int n, uint64_t budget, int j0, uint64_t count, u
 // and their batch orders.
 struct LearnedWs {
     int64_t* list;
-    uint16_t* feats;
-    orbg::MlpWorkspace fwd;
     uint8_t* orders;
     int64_t bytes;
 };
@@ -741,13 +739,8 @@ static LearnedWs learned_carve(void* base, int64_t batch)
     unsigned char* p = reinterpret_cast<unsigned char*>(base);
     int64_t o = 0;
     auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += (bytes + 255) & ~(int64_t)255; return r; };
-    const int64_t chunk = batch < MLP_BATCH_MAX ? batch : MLP_BATCH_MAX;
     w.list = (int64_t*)take(batch * 8);
-    w.feats = (uint16_t*)take(chunk * MLP_IN * 2);
     w.orders = (uint8_t*)take(batch * MLP_OUT);
-    const int64_t fwd = orbg::mlp_carve_forward(nullptr, chunk).bytes;
-    w.fwd = orbg::mlp_carve_forward(p ? p + o : nullptr, chunk);
-    o += fwd;
     w.bytes = o;
     return w;
 }
@@ -805,14 +798,10 @@ int orbg_decode_learned(const uint8_t* H, const float* llr, int n, int k, uint64
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ORBG_EHIP, "reading the count of listed blocks failed: %s", hipGetErrorString(e));
     if (rest) *rest = (int64_t)count;
-    // 2. features, network and batch order (batch 0 first) of the listed blocks
-    for (int64_t s = 0; s < (int64_t)count; s += MLP_BATCH_MAX) {
-        const int64_t c = (int64_t)count - s < MLP_BATCH_MAX ? (int64_t)count - s : MLP_BATCH_MAX;
-        e = orbg::mlp_features(llr, c, lw.feats, st, lw.list + s);
-        if (e == hipSuccess) e = orbg::mlp_forward(w, wb, lw.feats, c, lw.fwd.logits, lw.fwd, st);
-        if (e == hipSuccess) e = orbg::mlp_order(lw.fwd.logits, c, lw.orders + s * MLP_OUT, st, true);
-        if (e != hipSuccess) return fail(ORBG_EHIP, "network launch failed: %s", hipGetErrorString(e));
-    }
+    // 2. features, network and batch order (batch 0 first) of the listed blocks,
+    // one fused launch
+    e = orbg::mlp_infer(w, wb, llr, batch, lw.list, nullptr, (int64_t)count, nullptr, lw.orders, true, st);
+    if (e != hipSuccess) return fail(ORBG_EHIP, "network launch failed: %s", hipGetErrorString(e));
     if (order_out && (e = orbg::mlp_order_table(lw.orders, lw.list, (int64_t)count, batch, order_out, st)) != hipSuccess)
         return fail(ORBG_EHIP, "order table launch failed: %s", hipGetErrorString(e));
     if (count == 0) return ORBG_OK;
@@ -903,6 +892,22 @@ int orbg_mlp_adam(float* w, float* m, float* v, const float* grads, float lr, in
     if (step < 1) return fail(ORBG_EINVAL, "step = %d (steps count from 1)", step);
     const hipError_t e = orbg::mlp_adam(w, m, v, grads, lr, step, wb, wt, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "adam launch failed: %s", hipGetErrorString(e));
+}
+
+int orbg_mlp_infer(const float* w, const uint16_t* wb, const float* llr, int64_t llr_rows, const int64_t* ids,
+                   const uint16_t* x, int64_t batch, float* logits, uint8_t* order, int pin0, void* stream)
+{
+    g_err.clear();
+    if (batch < 0 || batch >= ((int64_t)1 << 31) * 32)
+        return fail(ORBG_EINVAL, "batch = %lld outside [0, 2^36)", (long long)batch);
+    if (llr && llr_rows < 0) return fail(ORBG_EINVAL, "llr_rows = %lld is negative", (long long)llr_rows);
+    if (pin0 != 0 && pin0 != 1) return fail(ORBG_EINVAL, "pin0 = %d is not 0 or 1", pin0);
+    if (!logits && !order) return fail(ORBG_EINVAL, "no output (logits and order are NULL)");
+    if (batch == 0) return ORBG_OK;
+    if (!w || !wb || (!llr && !x)) return fail(ORBG_EINVAL, "a device buffer is NULL");
+    const hipError_t e = orbg::mlp_infer(w, wb, llr, llr_rows, llr ? ids : nullptr, llr ? nullptr : x, batch, logits,
+                                         order, pin0 != 0, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ORBG_OK : fail(ORBG_EHIP, "inference launch failed: %s", hipGetErrorString(e));
 }
 
 int orbg_mlp_order(const float* logits, int64_t batch, uint8_t* order, void* stream)

@@ -248,6 +248,21 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
     write_copies(p, ww, wb, wt);
 }
 
+// One row's batch order (one logit per lane, all lanes active): lane e
+// returns the e-th batch to test.
+__device__ __forceinline__ uint8_t order_of_row(float logit, int pin0)
+{
+    const int lane = lane_id();
+    const float f = logit + 0.0f;                               // -0 -> +0
+    const uint32_t u = __float_as_uint(f);
+    const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
+    const uint32_t up = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f, NaN lowest
+    uint64_t key[1] = {((uint64_t)(~up) << 32) | (uint32_t)lane};          // ascending = decreasing f
+    if (pin0 && lane == 0) key[0] = 0ull;
+    bitonic_sort<1, uint64_t>(key);
+    return (uint8_t)(key[0] & 63u);
+}
+
 // Batch order: decreasing logit, ties (and +-0) to the lower index, NaN last;
 // pin0: batch 0 first whatever its logit, the others as before.  One wave per
 // row: key = (order-preserving bits of -logit) << 32 | index, sorted ascending
@@ -258,14 +273,7 @@ __global__ void __launch_bounds__(256) order_kernel(const float* __restrict__ lo
     const int lane = lane_id();
     const int64_t b = (int64_t)blockIdx.x * 4 + threadIdx.x / ORBG_WAVE;
     if (b >= batch) return;
-    const float f = logits[b * MLP_OUT + lane] + 0.0f;          // -0 -> +0
-    const uint32_t u = __float_as_uint(f);
-    const bool nan = (u & 0x7fffffffu) > 0x7f800000u;
-    const uint32_t up = nan ? 0u : ((u >> 31) ? ~u : (u | 0x80000000u));   // increasing with f, NaN lowest
-    uint64_t key[1] = {((uint64_t)(~up) << 32) | (uint32_t)lane};          // ascending = decreasing f
-    if (pin0 && lane == 0) key[0] = 0ull;
-    bitonic_sort<1, uint64_t>(key);
-    order[b * MLP_OUT + lane] = (uint8_t)(key[0] & 63u);
+    order[b * MLP_OUT + lane] = order_of_row(logits[b * MLP_OUT + lane], pin0);
 }
 
 // Order table of a gated decode: row b = identity for blocks decided by batch 0,
@@ -294,6 +302,147 @@ hipError_t mlp_order_table(const uint8_t* rows, const int64_t* ids, int64_t coun
 }
 
 // ---------------------------------------------------------------------------
+// Fused inference: (features,) the three layers and (the batch order) of
+// FT = 32 rows per 256-thread workgroup.  The rows' features and hidden
+// activations stay in LDS as BF16 [row][k], the 16-byte groups of a row
+// XOR-swizzled by the row index so that the 16 rows an MFMA fragment reads
+// fall in different banks; each wave computes a quarter of a layer's outputs
+// for all FT rows, its weight fragments read straight from global memory (the
+// BF16 weights, 224 KB, stay in L2).  Per output the k loop, the MFMA shape
+// and the epilogue are those of gemm_kernel, so the logits equal the unfused
+// forward's bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int FT = 32;
+
+// Element offset of (row, k) in a swizzled [FT][kdim] activation tile.
+__device__ __forceinline__ int swz(int row, int k, int kdim)
+{
+    return row * kdim + ((((k >> 3) ^ (row & 15))) << 3) + (k & 7);
+}
+
+// One layer: out(i, j) = sum_k in(i, k) W[j][k] for the FT rows and this
+// wave's N / 4 outputs.  HIDDEN: BF16(ReLU(. + bias)) to the swizzled LDS tile
+// `oh`; else . + bias as FP32 to `of` (row stride MLP_OUT).
+template <int K, int N, bool HIDDEN>
+__device__ __forceinline__ void fused_layer(const uint16_t* in, const uint16_t* __restrict__ W,
+                                            const float* __restrict__ bias, uint16_t* oh, float* of)
+{
+    const int lane = lane_id();
+    const int wave = threadIdx.x / ORBG_WAVE;
+    const int r = lane & 15, q = lane >> 4;
+    constexpr int NW = N / 4, CT = NW / 16, RT = FT / 16;
+    f4v acc[RT][CT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[a][c] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k = 0; k < K; k += 32) {
+        const int kk = k + 8 * q;
+        s8v fa[RT], fb[CT];
+#pragma unroll
+        for (int a = 0; a < RT; ++a) fa[a] = *reinterpret_cast<const s8v*>(in + swz(a * 16 + r, kk, K));
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            fb[c] = *reinterpret_cast<const s8v*>(W + (int64_t)(wave * NW + c * 16 + r) * K + kk);
+#pragma unroll
+        for (int a = 0; a < RT; ++a)
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, fa[a]),
+                                                                    __builtin_bit_cast(bf8v, fb[c]), acc[a][c], 0, 0, 0);
+    }
+    // lane holds D[4q + t][r] of each 16 x 16 tile, t = 0..3
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = a * 16 + 4 * q + t;
+                const int j = wave * NW + c * 16 + r;
+                const float v = acc[a][c][t];
+                if (HIDDEN) oh[swz(i, j, N)] = f32_to_bf16(fmaxf(v + bias[j], 0.f));
+                else of[i * MLP_OUT + j] = v + bias[j];
+            }
+}
+
+// FEAT: features of llr rows (ids[b], or b) made here, a row outside
+// [0, llr_rows) giving zero features; else read from x.  logits (or nullptr)
+// and order (or nullptr, ORDER false) receive the results.
+template <bool FEAT, bool ORDER>
+__global__ void __launch_bounds__(256)
+mlp_infer_kernel(const float* __restrict__ llr, int64_t llr_rows, const int64_t* __restrict__ ids,
+                 const uint16_t* __restrict__ x, int64_t batch, const float* __restrict__ w,
+                 const uint16_t* __restrict__ wb, float* __restrict__ logits, uint8_t* __restrict__ order, int pin0)
+{
+    __shared__ __align__(16) uint16_t sa[FT * MLP_HID];     // features (FT x 128), then h2
+    __shared__ __align__(16) uint16_t sb[FT * MLP_HID];     // h1, then the logits (FT x 64 FP32)
+    const int lane = lane_id();
+    const int wave = threadIdx.x / ORBG_WAVE;
+    const int64_t row0 = (int64_t)blockIdx.x * FT;
+    const int rows = (int)(batch - row0 < FT ? batch - row0 : FT);
+    if (FEAT) {
+        // sorted |LLR| / 8 in BF16 (as features_kernel); rows past the batch are zero
+        for (int rr = wave; rr < FT; rr += 4) {
+            uint32_t key[2] = {0u, 0u};
+            const int64_t src = rr < rows ? (ids ? ids[row0 + rr] : row0 + rr) : -1;
+            if (src >= 0 && src < llr_rows) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    key[j] = __float_as_uint(llr[src * MLP_IN + j * ORBG_WAVE + lane]) & 0x7fffffffu;
+            }
+            bitonic_sort<2, uint32_t>(key);
+            const uint32_t pair = (uint32_t)f32_to_bf16(__uint_as_float(key[0]) * 0.125f) |
+                                  ((uint32_t)f32_to_bf16(__uint_as_float(key[1]) * 0.125f) << 16);
+            *reinterpret_cast<uint32_t*>(sa + swz(rr, 2 * lane, MLP_IN)) = pair;
+        }
+    } else {
+        for (int g = threadIdx.x; g < FT * (MLP_IN / 8); g += 256) {
+            const int rr = g / (MLP_IN / 8), kg = g % (MLP_IN / 8);
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (rr < rows) v = *reinterpret_cast<const uint4*>(x + (row0 + rr) * MLP_IN + kg * 8);
+            *reinterpret_cast<uint4*>(sa + swz(rr, kg * 8, MLP_IN)) = v;
+        }
+    }
+    __syncthreads();
+    fused_layer<MLP_IN, MLP_HID, true>(sa, wb + MLP_OFF_W1, w + MLP_OFF_B1, sb, nullptr);
+    __syncthreads();
+    fused_layer<MLP_HID, MLP_HID, true>(sb, wb + MLP_OFF_W2, w + MLP_OFF_B2, sa, nullptr);
+    __syncthreads();
+    float* lg = reinterpret_cast<float*>(sb);
+    fused_layer<MLP_HID, MLP_OUT, false>(sa, wb + MLP_OFF_W3, w + MLP_OFF_B3, nullptr, lg);
+    __syncthreads();
+    if (logits != nullptr)
+        for (int e = threadIdx.x; e < rows * MLP_OUT; e += 256) logits[row0 * MLP_OUT + e] = lg[e];
+    if (ORDER)
+        for (int rr = wave; rr < FT; rr += 4) {
+            const uint8_t o = order_of_row(lg[rr * MLP_OUT + lane], pin0);
+            if (rr < rows) order[(row0 + rr) * MLP_OUT + lane] = o;
+        }
+}
+
+hipError_t mlp_infer(const float* w, const uint16_t* wb, const float* llr, int64_t llr_rows, const int64_t* ids,
+                     const uint16_t* x, int64_t batch, float* logits, uint8_t* order, bool pin0, hipStream_t st)
+{
+    if (batch <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((batch + FT - 1) / FT);
+    if (llr) {
+        if (order)
+            mlp_infer_kernel<true, true><<<grid, 256, 0, st>>>(llr, llr_rows, ids, x, batch, w, wb, logits, order, pin0);
+        else
+            mlp_infer_kernel<true, false><<<grid, 256, 0, st>>>(llr, llr_rows, ids, x, batch, w, wb, logits, order, pin0);
+    } else {
+        if (order)
+            mlp_infer_kernel<false, true><<<grid, 256, 0, st>>>(llr, llr_rows, ids, x, batch, w, wb, logits, order, pin0);
+        else
+            mlp_infer_kernel<false, false><<<grid, 256, 0, st>>>(llr, llr_rows, ids, x, batch, w, wb, logits, order,
+                                                                pin0);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 static int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
@@ -304,29 +453,24 @@ MlpWorkspace mlp_carve(void* base, int64_t batch)
     unsigned char* p = reinterpret_cast<unsigned char*>(base);
     int64_t o = 0;
     auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += align256(bytes); return r; };
-    const int splits = (int)((batch + MLP_KCHUNK - 1) / MLP_KCHUNK);
+    // weight gradients reduce over the batch: enough splits to fill the device
+    // (at least MLP_KCHUNK_MIN rows each, at most MLP_SPLITS_MAX of them)
+    int64_t kchunk = (batch + MLP_SPLITS_MAX - 1) / MLP_SPLITS_MAX;
+    kchunk = kchunk < MLP_KCHUNK_MIN ? MLP_KCHUNK_MIN : (kchunk + 31) / 32 * 32;
+    const int splits = (int)((batch + kchunk - 1) / kchunk);
     w.h1 = (uint16_t*)take(batch * MLP_HID * 2);
     w.h2 = (uint16_t*)take(batch * MLP_HID * 2);
     w.logits = (float*)take(batch * MLP_OUT * 4);
     w.dl = (uint16_t*)take(batch * MLP_OUT * 2);
     w.dz2 = (uint16_t*)take(batch * MLP_HID * 2);
     w.dz1 = (uint16_t*)take(batch * MLP_HID * 2);
-    w.part = (float*)take((int64_t)splits * MLP_HID * MLP_HID * 4);
+    // (room for the most splits any batch of this size or smaller uses, so the
+    // work space grows with the batch)
+    const int64_t room = (batch + MLP_KCHUNK_MIN - 1) / MLP_KCHUNK_MIN;
+    w.part = (float*)take((room < MLP_SPLITS_MAX ? room : MLP_SPLITS_MAX) * MLP_HID * MLP_HID * 4);
     w.rowloss = (float*)take(batch * 4);
     w.splits = splits;
-    w.bytes = o;
-    return w;
-}
-
-MlpWorkspace mlp_carve_forward(void* base, int64_t batch)
-{
-    MlpWorkspace w = {};
-    unsigned char* p = reinterpret_cast<unsigned char*>(base);
-    int64_t o = 0;
-    auto take = [&](int64_t bytes) { void* r = p ? p + o : nullptr; o += align256(bytes); return r; };
-    w.h1 = (uint16_t*)take(batch * MLP_HID * 2);
-    w.h2 = (uint16_t*)take(batch * MLP_HID * 2);
-    w.logits = (float*)take(batch * MLP_OUT * 4);
+    w.kchunk = (int)kchunk;
     w.bytes = o;
     return w;
 }
@@ -377,33 +521,33 @@ hipError_t mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, 
     hipError_t e = mlp_forward(w, wb, x, batch, ws.logits, ws, st);
     if (e != hipSuccess) return e;
     const int Bm = (int)batch;
-    const int S = ws.splits;
+    const int S = ws.splits, KC = ws.kchunk;
     softmax_ce_kernel<<<(unsigned)((batch + 3) / 4), 256, 0, st>>>(ws.logits, labels, batch, ws.dl, ws.rowloss);
     sum_kernel<<<1, 256, 0, st>>>(ws.rowloss, batch, 1.0f / (float)batch, loss);
     // layer 3: dW3 = dl^T h2, db3 = colsum(dl), dz2 = (dl W3) * [h2 > 0]
-    gemm<false, false, EPI_PARTIAL>(ws.dl, 1, MLP_OUT, ws.h2, MLP_HID, 1, MLP_OUT, MLP_HID, Bm, S, MLP_KCHUNK, nullptr,
+    gemm<false, false, EPI_PARTIAL>(ws.dl, 1, MLP_OUT, ws.h2, MLP_HID, 1, MLP_OUT, MLP_HID, Bm, S, KC, nullptr,
                                     ws.part, 0, nullptr, 0, st);
     reduce_partials_kernel<<<(MLP_OUT * MLP_HID + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_OUT * MLP_HID,
                                                                            grads + MLP_OFF_W3);
-    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dl, batch, MLP_OUT, MLP_KCHUNK, ws.part);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dl, batch, MLP_OUT, KC, ws.part);
     reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_OUT, grads + MLP_OFF_B3);
     gemm<true, true, EPI_MASKED>(ws.dl, MLP_OUT, 1, wt + MLP_T_W3, 1, MLP_OUT, Bm, MLP_HID, MLP_OUT, 1, MLP_OUT,
                                  nullptr, ws.dz2, MLP_HID, ws.h2, MLP_HID, st);
     // layer 2
-    gemm<false, false, EPI_PARTIAL>(ws.dz2, 1, MLP_HID, ws.h1, MLP_HID, 1, MLP_HID, MLP_HID, Bm, S, MLP_KCHUNK,
+    gemm<false, false, EPI_PARTIAL>(ws.dz2, 1, MLP_HID, ws.h1, MLP_HID, 1, MLP_HID, MLP_HID, Bm, S, KC,
                                     nullptr, ws.part, 0, nullptr, 0, st);
     reduce_partials_kernel<<<(MLP_HID * MLP_HID + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_HID * MLP_HID,
                                                                            grads + MLP_OFF_W2);
-    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz2, batch, MLP_HID, MLP_KCHUNK, ws.part);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz2, batch, MLP_HID, KC, ws.part);
     reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_HID, grads + MLP_OFF_B2);
     gemm<true, true, EPI_MASKED>(ws.dz2, MLP_HID, 1, wt + MLP_T_W2, 1, MLP_HID, Bm, MLP_HID, MLP_HID, 1, MLP_HID,
                                  nullptr, ws.dz1, MLP_HID, ws.h1, MLP_HID, st);
     // layer 1
-    gemm<false, false, EPI_PARTIAL>(ws.dz1, 1, MLP_HID, x, MLP_IN, 1, MLP_HID, MLP_IN, Bm, S, MLP_KCHUNK, nullptr,
+    gemm<false, false, EPI_PARTIAL>(ws.dz1, 1, MLP_HID, x, MLP_IN, 1, MLP_HID, MLP_IN, Bm, S, KC, nullptr,
                                     ws.part, 0, nullptr, 0, st);
     reduce_partials_kernel<<<(MLP_HID * MLP_IN + 255) / 256, 256, 0, st>>>(ws.part, S, MLP_HID * MLP_IN,
                                                                           grads + MLP_OFF_W1);
-    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz1, batch, MLP_HID, MLP_KCHUNK, ws.part);
+    colsum_kernel<<<dim3(1, S), 256, 0, st>>>(ws.dz1, batch, MLP_HID, KC, ws.part);
     reduce_partials_kernel<<<1, 256, 0, st>>>(ws.part, S, MLP_HID, grads + MLP_OFF_B1);
     return hipGetLastError();
 }

@@ -19,7 +19,8 @@
 #define MLP_T_W2 (MLP_T_W1 + MLP_IN * MLP_HID)
 #define MLP_T_W3 (MLP_T_W2 + MLP_HID * MLP_HID)
 #define MLP_NTRANS (MLP_T_W3 + MLP_HID * MLP_OUT)
-#define MLP_KCHUNK 1024      // batch rows per split of a weight-gradient GEMM
+#define MLP_KCHUNK_MIN 256   // fewest batch rows per split of a weight-gradient GEMM
+#define MLP_SPLITS_MAX 64    // most splits of a weight-gradient GEMM
 #define MLP_BATCH_MAX (1 << 20)
 
 namespace orbg {
@@ -33,15 +34,14 @@ struct MlpWorkspace {
     uint16_t* dz1;
     float* part;
     float* rowloss;
-    int splits;
+    int splits;              // batch rows split into `splits` chunks of `kchunk` (a multiple of 32)
+    int kchunk;
     int64_t bytes;
 };
 
 // Carves the work space of a `batch`-row call out of `base` (base may be
 // nullptr to only compute .bytes).
 MlpWorkspace mlp_carve(void* base, int64_t batch);
-// The forward's part of it (h1, h2, logits).
-MlpWorkspace mlp_carve_forward(void* base, int64_t batch);
 
 hipError_t mlp_features(const float* llr, int64_t batch, uint16_t* x, hipStream_t st, const int64_t* ids = nullptr);
 hipError_t mlp_prepare(const float* w, uint16_t* wb, uint16_t* wt, hipStream_t st);
@@ -53,6 +53,12 @@ hipError_t mlp_backward(const float* w, const uint16_t* wb, const uint16_t* wt, 
 hipError_t mlp_adam(float* w, float* m, float* v, const float* g, float lr, int step, uint16_t* wb, uint16_t* wt,
                     hipStream_t st);
 hipError_t mlp_order(const float* logits, int64_t batch, uint8_t* order, hipStream_t st, bool pin0 = false);
+// Fused inference without a work space: features of llr rows (ids[b], or b;
+// rows outside [0, llr_rows) read as zeros) or the given features x (llr ==
+// nullptr), the three layers, and the logits and/or the batch order (either may
+// be nullptr, not both).
+hipError_t mlp_infer(const float* w, const uint16_t* wb, const float* llr, int64_t llr_rows, const int64_t* ids,
+                     const uint16_t* x, int64_t batch, float* logits, uint8_t* order, bool pin0, hipStream_t st);
 hipError_t mlp_order_table(const uint8_t* rows, const int64_t* ids, int64_t count, int64_t batch, uint8_t* order,
                            hipStream_t st);
 

@@ -183,3 +183,30 @@ def test_mline_argument_errors(n, k, budget, seg, jdiv, bufs, msg):
     p = ctypes.c_void_p(8) if bufs else None
     rc = L.orbg_decode_mline(H.ctypes.data_as(ctypes.c_void_p), p, n, k, budget, 4, seg, jdiv, p, p, p, None, None)
     assert rc == -1 and msg in L.orbg_last_error().decode()
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("negative_batch", "batch = -1"),
+    ("no_output", "no output"),
+    ("no_input", "device buffer is NULL"),
+    ("negative_rows", "llr_rows = -3"),
+    ("pin0", "pin0 = 2"),
+])
+def test_mlp_infer_argument_errors(case, msg):
+    """The fused inference entry point's checks (no device work is reached)."""
+    L = binding.load()
+    p = ctypes.c_void_p(8)
+    args = dict(w=p, wb=p, llr=p, rows=4, ids=None, x=None, batch=4, logits=p, order=None, pin0=0)
+    if case == "negative_batch":
+        args["batch"] = -1
+    elif case == "no_output":
+        args["logits"] = None
+    elif case == "no_input":
+        args["llr"] = None
+    elif case == "negative_rows":
+        args["rows"] = -3
+    elif case == "pin0":
+        args["pin0"] = 2
+    rc = L.orbg_mlp_infer(args["w"], args["wb"], args["llr"], args["rows"], args["ids"], args["x"], args["batch"],
+                          args["logits"], args["order"], args["pin0"], None)
+    assert rc == -1 and msg in L.orbg_last_error().decode()

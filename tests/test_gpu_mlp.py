@@ -70,6 +70,52 @@ def test_forward_matches_reference(gpu_device, N):
     assert (wt == want_t).all()
 
 
+@pytest.mark.parametrize("N", [1, 31, 1000])
+def test_fused_inference_equals_unfused(gpu_device, N):
+    """orbg_mlp_infer (features, three layers with on-chip activations, order in
+    one launch) against the unfused kernels, bit for bit: logits from given
+    features, from llr rows, and from an id list with ids outside the llr rows
+    (zero features); orders against orbg_mlp_order, with batch 0 pinned first."""
+    print(f"fused inference N={N}", flush=True)
+    w = M.init(7)
+    d = M.unflatten(w.astype(np.float64))
+    rng = np.random.default_rng(100 + N)
+    for b in ("b1", "b2", "b3"):
+        d[b][:] = rng.standard_normal(d[b].shape) * 0.1
+    w = M.flatten(d).astype(np.float32)
+    p = _setup(w, gpu_device)
+    llr = torch.from_numpy((rng.standard_normal((N, 128)) * 6).astype(np.float32)).to(gpu_device)
+    x = learned.features(llr)
+    ref = p.logits(x)
+    lg = torch.empty((N, 64), dtype=torch.float32, device=gpu_device)
+    binding.orbg_mlp_infer(p.w, p.wb, x=x, logits=lg)
+    torch.cuda.synchronize()
+    assert torch.equal(lg, ref)
+    lg2 = torch.empty_like(lg)
+    od2 = torch.empty((N, 64), dtype=torch.uint8, device=gpu_device)
+    binding.orbg_mlp_infer(p.w, p.wb, llr=llr, logits=lg2, order=od2)
+    want_od = torch.empty_like(od2)
+    binding.orbg_mlp_order(ref, want_od)
+    torch.cuda.synchronize()
+    assert torch.equal(lg2, ref) and torch.equal(od2, want_od)
+    # an id list: a permutation of the rows with two ids past the array
+    ids_np = rng.permutation(N).astype(np.int64)
+    ids_np = np.concatenate([ids_np, [-1, N + 5]])
+    ids = torch.from_numpy(ids_np).to(gpu_device)
+    lg3 = torch.empty((ids.numel(), 64), dtype=torch.float32, device=gpu_device)
+    od3 = torch.empty((ids.numel(), 64), dtype=torch.uint8, device=gpu_device)
+    binding.orbg_mlp_infer(p.w, p.wb, llr=llr, ids=ids, logits=lg3, order=od3, pin0=True)
+    zero = p.logits(torch.zeros((1, 128), dtype=torch.int16, device=gpu_device))
+    want3 = torch.cat([ref[ids[:N]], zero, zero])
+    pinned = want3.clone()
+    pinned[:, 0] = float("inf")
+    want_od3 = torch.empty_like(od3)
+    binding.orbg_mlp_order(pinned, want_od3)
+    torch.cuda.synchronize()
+    assert torch.equal(lg3, want3) and torch.equal(od3, want_od3)
+    assert (od3[:, 0] == 0).all()
+
+
 @pytest.mark.parametrize("N", [7, 1000, 2500])
 def test_backward_matches_reference(gpu_device, N):
     w = M.init(5)
