@@ -108,6 +108,19 @@ int main()
     EXPECT(orbg_mlp_adam((float*)p, (float*)p, (float*)p, (float*)p, 0.1f, 0, (uint16_t*)p, (uint16_t*)p, nullptr),
            ORBG_EINVAL, "step");
     EXPECT(orbg_mlp_order(nullptr, 4, u8, nullptr), ORBG_EINVAL, "NULL");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, (float*)p, 4, nullptr, nullptr, -1, (float*)p, nullptr, 0,
+                          nullptr),
+           ORBG_EINVAL, "batch");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, (float*)p, 4, nullptr, nullptr, 4, nullptr, nullptr, 0, nullptr),
+           ORBG_EINVAL, "no output");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, nullptr, 4, nullptr, nullptr, 4, (float*)p, nullptr, 0, nullptr),
+           ORBG_EINVAL, "NULL");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, (float*)p, -3, nullptr, nullptr, 4, (float*)p, nullptr, 0, nullptr),
+           ORBG_EINVAL, "llr_rows");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, (float*)p, 4, nullptr, nullptr, 4, (float*)p, u8, 2, nullptr),
+           ORBG_EINVAL, "pin0");
+    EXPECT(orbg_mlp_infer((float*)p, (uint16_t*)p, (float*)p, 4, nullptr, nullptr, 4, (float*)p, u8, 1, nullptr),
+           ORBG_EHIP, "inference launch failed");
     if (orbg_learned_workspace_bytes(-1) != -1) { std::fprintf(stderr, "learned workspace bytes of -1\n"); ++fails; }
     std::vector<uint8_t> H128(23 * 128, 0);
     for (int r = 0; r < 23; ++r) H128[r * 128 + 105 + r] = 1;

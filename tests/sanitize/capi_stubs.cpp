@@ -33,12 +33,6 @@ MlpWorkspace mlp_carve(void*, int64_t batch)
     w.bytes = batch * 4096;
     return w;
 }
-MlpWorkspace mlp_carve_forward(void*, int64_t batch)
-{
-    MlpWorkspace w = {};
-    w.bytes = batch * 2048;
-    return w;
-}
 hipError_t mlp_features(const float*, int64_t, uint16_t*, hipStream_t, const int64_t*) { return hipErrorNotSupported; }
 hipError_t mlp_prepare(const float*, uint16_t*, uint16_t*, hipStream_t) { return hipErrorNotSupported; }
 hipError_t mlp_forward(const float*, const uint16_t*, const uint16_t*, int64_t, float*, const MlpWorkspace&,
@@ -57,6 +51,11 @@ hipError_t mlp_adam(float*, float*, float*, const float*, float, int, uint16_t*,
 }
 hipError_t mlp_order(const float*, int64_t, uint8_t*, hipStream_t, bool) { return hipErrorNotSupported; }
 hipError_t mlp_order_table(const uint8_t*, const int64_t*, int64_t, int64_t, uint8_t*, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+hipError_t mlp_infer(const float*, const uint16_t*, const float*, int64_t, const int64_t*, const uint16_t*, int64_t,
+                     float*, uint8_t*, bool, hipStream_t)
 {
     return hipErrorNotSupported;
 }
