@@ -166,7 +166,8 @@ def query_breakdown(q, ab, err, budget, sweep=(10 ** 2, 10 ** 3, 10 ** 4, 10 ** 
 # counters stay valid while these are unchanged.
 DECODE_SOURCES = ("decode.hip", "decode_impl.h", "decode_nk1.hip", "decode_nk2.hip", "decode_nk4.hip", "decode_nk8.hip",
                   "decode_nk16.hip", "orbg_device.h", "orbg_internal.h", "orbg_kernels.h", "schedule.hip")
-MLINE_SOURCES = ("mline.hip", "orbg_mline.h", "orbg_device.h", "orbg_internal.h")
+MLINE_SOURCES = ("mline.hip", "mline_impl.h", "mline_m1.hip", "mline_m2.hip", "mline_m3.hip", "mline_m4.hip", "orbg_mline.h",
+                 "orbg_device.h", "orbg_internal.h")
 
 
 def kernel_fingerprint(sources=DECODE_SOURCES) -> str:

@@ -36,5 +36,12 @@ constexpr size_t subset_table_words() { return (size_t)(ORBG_ML_LMAX + 1) * (ORB
 
 hipError_t build_subset_table(uint32_t* t, hipStream_t stream);
 hipError_t launch_mline(const MlineArgs& a, int grid, hipStream_t stream);
+// The kernels for fits of at most MM segments (one translation unit each).
+template <int MM>
+hipError_t launch_mline_m(const MlineArgs& a, int grid, hipStream_t stream);
+extern template hipError_t launch_mline_m<1>(const MlineArgs&, int, hipStream_t);
+extern template hipError_t launch_mline_m<2>(const MlineArgs&, int, hipStream_t);
+extern template hipError_t launch_mline_m<3>(const MlineArgs&, int, hipStream_t);
+extern template hipError_t launch_mline_m<4>(const MlineArgs&, int, hipStream_t);
 
 }  // namespace orbg
