@@ -24,7 +24,7 @@ CACHE = os.path.join(HERE, "tuned.json")
 
 KNOBS = {
     "split_steps": [0, 16, 32, 64, 128, 256],
-    "workgroups_per_cu": [8, 16, 24, 32, 48],
+    "workgroups_per_cu": [8, 16, 24, 28, 32, 48],
     "chunk": [0, 8, 16, 32, 64],
     "heavy_waves": [4, 8, 16],
     "heavy_workgroups_per_cu": [1, 2, 4, 8],

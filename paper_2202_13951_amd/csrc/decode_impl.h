@@ -792,30 +792,70 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     uint64_t hrow0[NKMAX];
     if (HOIST) load_hrows<NKMAX>(s_rows, codes.c[0].m, hrow0);
 
-    // work cursor (wave-uniform): k-th slice visited, its range [lo, hi), end of
-    // the current chunk; `pend` (lane 0) receives the next chunk's counter value
-    const int home = (int)(blockIdx.x % ORBG_XCDS);
-    int k = 0;
-    int64_t lo = nblocks * home / ORBG_XCDS, hi = nblocks * (home + 1) / ORBG_XCDS, end = 0;
+    // Work cursor (wave-uniform).  The blocks are dealt to ORBG_SLICES slices in
+    // stripes of Z blocks: stripe g (blocks [g Z, (g + 1) Z)) goes to slice
+    // g % S, so every slice holds the same mix of the batch (a batch laid out by
+    // channel condition still gives slices of equal cost, which drain
+    // together).  Z is a whole number of chunks, up to ORBG_STRIPE of them, and
+    // small enough that each slice gets about 8 stripes or more.  Workgroup w starts on slice w % S, which lies on its
+    // own XCD (workgroups are dealt round-robin to the 8 XCDs).  A slice's
+    // counter counts the blocks claimed, `chunk` at a time (chunks never cross a
+    // stripe, Z being a multiple of the chunk); `pend` (lane 0) receives the
+    // next chunk's counter value, claimed when a chunk starts.  Increments of
+    // one counter queue one behind another (of the order of 0.1 us each), so
+    // many slices keep few waves on each counter: with one per XCD, the one
+    // increment every wave makes cost about 0.1 ms per launch, whatever the
+    // number of blocks.
+    const int64_t zc = nblocks / ((int64_t)ORBG_SLICES * chunk * 8);
+    const int64_t Z = (int64_t)chunk * (zc < 1 ? 1 : zc > ORBG_STRIPE ? ORBG_STRIPE : zc);
+    const int64_t nstripes = (nblocks + Z - 1) / Z;
+    // blocks in slice x: stripes x, x + S, ... (the batch's last stripe may be short)
+    auto slice_len = [&](int64_t x) -> int64_t {
+        if (x >= nstripes) return 0;
+        const int64_t cnt = (nstripes - 1 - x) / ORBG_SLICES + 1;
+        const int64_t last = (x + (cnt - 1) * ORBG_SLICES) * Z;
+        return (cnt - 1) * Z + (nblocks - last < Z ? nblocks - last : Z);
+    };
+    const int home = (int)(blockIdx.x % ORBG_SLICES);
+    int slice = home;
+    int64_t len = uniform_i64(slice_len(home)), end = 0;
     unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(home);
     unsigned long long pend = 0;
-    // start of the next chunk (its end in `end`), or -1 when every slice is
-    // drained.  Every cursor value goes through readfirstlane so that it stays
-    // in scalar registers and the branches on it stay scalar.
+    // The slice to move to when the current one is drained, or -1 when all are:
+    // lane x reads slice x's counter (one coherent load, no increment), and
+    // since a counter only grows, a slice seen drained stays drained.  The pick
+    // is the nearest open slice after the home slice on the same XCD, else the
+    // nearest open one (bit j of rot: slice (home + j) % S; j a multiple of 8:
+    // the same XCD).
+    auto next_open = [&]() -> int {
+        static_assert(ORBG_SLICES == ORBG_WAVE, "one lane per slice");
+        static_assert(ORBG_XCDS == 8, "slices of one XCD are 8 apart");
+        const unsigned long long v =
+            __hip_atomic_load(ctrs + ORBG_CTR_SLICE(lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t rot = __builtin_rotateright64(ballot((int64_t)v < slice_len(lane)), (unsigned)home);
+        if (rot == 0) return -1;
+        constexpr uint64_t SAME_XCD = 0x0101010101010101ull;
+        const uint64_t pick = (rot & SAME_XCD) != 0 ? (rot & SAME_XCD) : rot;
+        return (int)uniform_u32((uint32_t)((home + __builtin_ctzll(pick)) % ORBG_SLICES));
+    };
+    // first block of the next chunk (its end in `end`), or -1 when every slice
+    // is drained.  Every cursor value goes through readfirstlane so that it
+    // stays in scalar registers and the branches on it stay scalar.  Each failed
+    // increment leaves its slice seen drained by the next snapshot, so the loop
+    // ends after at most ORBG_SLICES of them.
     auto next_chunk = [&]() -> int64_t {
         int64_t s;
         for (;;) {
-            s = uniform_i64(lo + (int64_t)uniform_u64(pend));
-            const bool hit = s < hi;
+            const int64_t p = uniform_i64((int64_t)uniform_u64(pend));
+            const bool hit = p < len;
             if (hit) {
-                end = uniform_i64((s + chunk < hi) ? s + chunk : hi);
+                s = uniform_i64((p / Z * ORBG_SLICES + slice) * Z + p % Z);
+                end = uniform_i64(s + (len - p < chunk ? len - p : chunk));
             } else {
-                k = (int)uniform_u32((uint32_t)k + 1u);
-                if (k == ORBG_XCDS) return -1;
-                const int xs = (home + k) % ORBG_XCDS;
-                lo = uniform_i64(nblocks * xs / ORBG_XCDS);
-                hi = uniform_i64(nblocks * (xs + 1) / ORBG_XCDS);
-                ctr = ctrs + ORBG_CTR_SLICE(xs);
+                slice = next_open();
+                if (slice < 0) return -1;
+                len = uniform_i64(slice_len(slice));
+                ctr = ctrs + ORBG_CTR_SLICE(slice);
             }
             // one lane increments; the loop leaves only after this branch has joined
             if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
@@ -848,6 +888,63 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     constexpr int K = ScreenDepth<NKMAX>::value;
     auto screen = [&](int64_t s, int64_t e) -> uint64_t {
         uint64_t left = 0;
+        if constexpr (!MIXED) {
+            // One code: nothing per row is held across the loads but the
+            // fetched values.  A row's output index and offset are computed
+            // again from the group start when it is screened (the group start
+            // and row count pass through an empty asm statement, so the two
+            // computations stay apart): held, the K offsets and their masks
+            // exceed the scalar registers, and their spills to vector lanes
+            // cost more vector instructions than the screening itself.
+            const CodeDesc& c = codes.c[0];
+            const int n = c.n;
+            auto out_index = [&](int64_t b) -> int64_t { return ids ? scalar_load_i64(ids, b) : b; };
+            for (int64_t g = s; g < e; g += K) {
+                float xs[K][NKMAX];
+                uint32_t first[K];
+                const uint32_t cnt = uniform_u32((uint32_t)((e - g) < K ? (e - g) : K));
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    const bool ok = (uint32_t)kk < cnt;
+                    const int64_t oid = ok ? out_index(g + kk) : 0;
+                    load_row_buf<NKMAX>(make_buf(llr + oid * n, ok ? (uint32_t)n * 4u : 0u), xs[kk]);
+                    first[kk] = ORDERED ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(
+                                              make_buf(order + (ok ? g + kk : 0) * 64, ok ? 1u : 0u), 0, 0, 0)
+                                        : 0u;
+                }
+                int64_t g2 = g;
+                uint32_t cnt2 = cnt;
+                asm volatile("" : "+s"(g2), "+s"(cnt2));
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    if ((uint32_t)kk < cnt2) {
+                        uint64_t hr[NKMAX];
+                        if (HOIST) {
+#pragma unroll
+                            for (int j = 0; j < NKMAX; ++j) hr[j] = hrow0[j];
+                        } else {
+                            load_hrows<NKMAX>(s_rows, c.m, hr);
+                        }
+                        bool yb[NKMAX];
+                        const S s0 = hard_decision<NKMAX, S>(xs[kk], n, hr, yb);
+                        const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u) &&
+                                          !(ONELINE && j0_out != nullptr);
+                        if (done) {
+                            const int64_t oid = out_index(g2 + kk);
+                            const buf_t cwr = make_buf(cw + oid * n, (uint32_t)n);
+#pragma unroll
+                            for (int j = 0; j < NKMAX; ++j)
+                                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, j * ORBG_WAVE + lane,
+                                                                     0, 0);
+                            write_result(queries + oid, abandoned + oid, 1u, false);
+                        } else {
+                            left |= 1ull << (g2 + kk - s);
+                        }
+                    }
+                }
+            }
+            return left;
+        }
         for (int64_t g = s; g < e; g += K) {
             float xs[K][NKMAX];
             int cis[K];

@@ -67,11 +67,14 @@ struct DecodeArgs {
     LaunchParams p;
 };
 
-// Counter slots (u64 index, each on its own 256-byte line).
-#define ORBG_CTR_SLICE(x) ((x) * 32)
-#define ORBG_CTR_HEAVY_COUNT (8 * 32)
-#define ORBG_CTR_HEAVY_NEXT (9 * 32)
-#define ORBG_CTR_WORDS (10 * 32)
+// Work slices of the light pass (8 per XCD), their stripe length in chunks, and
+// the counter slots (u64 index, each on its own 128-byte line).
+#define ORBG_SLICES 64
+#define ORBG_STRIPE 64
+#define ORBG_CTR_SLICE(x) ((x) * 16)
+#define ORBG_CTR_HEAVY_COUNT (ORBG_SLICES * 16)
+#define ORBG_CTR_HEAVY_NEXT ((ORBG_SLICES + 1) * 16)
+#define ORBG_CTR_WORDS ((ORBG_SLICES + 2) * 16)
 
 hipError_t launch_decode(const DecodeArgs& a, hipStream_t stream);
 
