@@ -455,6 +455,27 @@ __device__ __forceinline__ S entry_syndrome(const BlockLds<S>& L, uint2 ent)
     return v;
 }
 
+// Two steps' syndromes: both entries' first four table reads go out together,
+// then one ballot decides whether either needs its last four slots.
+template <typename S>
+__device__ __forceinline__ void entry_syndrome2(const BlockLds<S>& L, uint2 ea, uint2 eb, S& va, S& vb)
+{
+    const S a0 = L.T[ea.x & 0xffu], a1 = L.h[(ea.x >> 8) & 0xffu], a2 = L.h[(ea.x >> 16) & 0xffu],
+            a3 = L.h[ea.x >> 24];
+    const S b0 = L.T[eb.x & 0xffu], b1 = L.h[(eb.x >> 8) & 0xffu], b2 = L.h[(eb.x >> 16) & 0xffu],
+            b3 = L.h[eb.x >> 24];
+    va = xor3<S>(a0, a1, a2) ^ a3;
+    vb = xor3<S>(b0, b1, b2) ^ b3;
+    if (ballot((ea.y | eb.y) != 0u) != 0ull) {
+        const S c0 = L.h[ea.y & 0xffu], c1 = L.h[(ea.y >> 8) & 0xffu];
+        const S c2 = L.h[(ea.y >> 16) & 0xffu], c3 = L.h[ea.y >> 24];
+        const S d0 = L.h[eb.y & 0xffu], d1 = L.h[(eb.y >> 8) & 0xffu];
+        const S d2 = L.h[(eb.y >> 16) & 0xffu], d3 = L.h[eb.y >> 24];
+        va = xor3<S>(xor3<S>(va, c0, c1), c2, c3);
+        vb = xor3<S>(xor3<S>(vb, d0, d1), d2, d3);
+    }
+}
+
 // Step 5: the hard decision with the winning entry's ranks flipped, stored
 // through the row's buffer descriptor (lanes past n store nothing).  The
 // received position of each flipped rank is wave-uniform; the lane holding it
@@ -511,8 +532,9 @@ __device__ __forceinline__ void write_offset(int32_t* j0_out, int j0)
 
 // Light pass, one block.  Returns true if the block is left for the heavy pass
 // (then nothing is written but the 1-line offset).  ONELINE: the block's fitted
-// offset (written to j0_out when that is not null) picks its schedule.
-template <int NK, bool ORDERED, typename S, bool ONELINE>
+// offset (written to j0_out when that is not null) picks its schedule.  PAIRS:
+// the search tests two steps per branch.
+template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS>
 __device__ __forceinline__ bool light_block(
     const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
     BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
@@ -582,31 +604,53 @@ __device__ __forceinline__ bool light_block(
         const uint32_t T = (lim + ORBG_WAVE - 1) / ORBG_WAVE;
         // entries of step u: a schedule holds whole batches of 64 entries and
         // ORBG_SCHED_PAD zero batches after its last one, so the loads for up to
-        // three steps past the end stay inside it and need no bounds check
+        // five steps past the end stay inside it and need no bounds check
         auto entries = [&](uint32_t u) -> uint2 {
             return load_entry(sched, batch_at<ORDERED>(ordv, u) * ORBG_WAVE + (uint32_t)lane);
         };
-        // the first three steps' entries do not depend on the block's order of
-        // reliability: they load while the ranks are sorted (1-line: after the
-        // ranking that picks the schedule)
+        // the first three (PAIRS: four) steps' entries do not depend on the
+        // block's order of reliability: they load while the ranks are sorted
+        // (1-line: after the ranking that picks the schedule)
         // (t0 = 1: batch 0 is known to hold no member and is counted, not tested)
-        uint2 e0 = entries(t0), e1 = entries(t0 + 1), e2 = entries(t0 + 2), e3 = make_uint2(0u, 0u);
+        uint2 e0 = entries(t0), e1 = entries(t0 + 1), e2 = entries(t0 + 2);
+        uint2 e3 = PAIRS ? entries(t0 + 3) : make_uint2(0u, 0u);
         uint32_t t = t0;
         // the search stops at step tend: the end of the queries, or the split
         // point if that comes first
         const uint32_t tend = (split_steps != 0 && split_steps < T) ? split_steps : T;
-        // One step: load the entries of step t + 3, test those of step t, move
-        // to step t + 1.  The search state is t, the steps left before tend and
-        // the ballot of the last step's hits: true when the search stops (a hit,
-        // or step tend reached).  Four register sets rotate, so a load is
-        // consumed three steps after it was issued.
+        // The search state is t, the steps left before tend and the ballot of
+        // the hits of the step that ended it: a step function returns true when
+        // the search stops (a hit, or step tend reached).
         uint64_t hits = 0;
         uint32_t rem = tend > t0 ? tend - t0 : 0u;
+        // One step: load the entries of step t + 3, test those of step t, move
+        // to step t + 1.  Four register sets rotate, so a load is consumed
+        // three steps after it was issued.
         auto step = [&](const uint2 cur, uint2& ahead) -> bool {
             ahead = entries(t + 3);
             hits = ballot(entry_syndrome<S>(L, cur) == 0);
             ++t;
             --rem;
+            return hits != 0 || rem == 0;
+        };
+        // PAIRS: steps t and t + 1 under one branch (a hit in step t comes
+        // first; step t + 1 counts only if it lies before tend), their eight
+        // table reads out together, and the pair's registers then take the
+        // entries of steps t + 4 and t + 5: half the scalar bookkeeping per
+        // step.  It needs a few more registers, so only the kernels that have
+        // them use it (one code, two keys per lane).
+        auto step2 = [&](uint2& ea, uint2& eb) -> bool {
+            S va, vb;
+            entry_syndrome2<S>(L, ea, eb, va, vb);
+            // the pair's registers take steps t + 4 and t + 5 once read
+            ea = entries(t + 4);
+            eb = entries(t + 5);
+            const uint64_t ha = ballot(va == 0);
+            const uint64_t hb = ballot(vb == 0);
+            const uint32_t adv = (ha != 0 || rem == 1) ? 1u : 2u;
+            hits = adv == 1u ? ha : hb;
+            t += adv;
+            rem -= adv;
             return hits != 0 || rem == 0;
         };
         // 0 (go on), 1 (hit), 2 (no hit within the budget), 3 (split point).
@@ -638,25 +682,46 @@ __device__ __forceinline__ bool light_block(
         // A search that stops after step 0 (split_steps = 1) always tries: it
         // never needs more ranks than the first batch reaches.
         int r = 0;
-        bool resume = false;                  // step 0 already tested
+        bool resume = false;                  // step 0 already tested (one-step loop)
         uint32_t idx1 = 0;
         lazy.tries = uniform_u32(lazy.tries + 1u);
         if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u || split_steps == 1u) &&
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
             first_tables<S>(idx1, c.rdepth0, cols, s0, L);
-            r = outcome(step(e0, e3));
-            resume = true;
+            if constexpr (PAIRS) {
+                // step 0 alone; the entries move down one step, the next load
+                // taking step 4
+                const uint2 e4 = entries(t + 4);
+                hits = ballot(entry_syndrome<S>(L, e0) == 0);
+                ++t;
+                --rem;
+                r = outcome(hits != 0 || rem == 0);
+                e0 = e1;
+                e1 = e2;
+                e2 = e3;
+                e3 = e4;
+            } else {
+                r = outcome(step(e0, e3));
+                resume = true;
+            }
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
         if (r == 0 && rem == 0) r = outcome(true);          // nothing left to test after batch 0
         if (r == 0) {
             if (!ONELINE) rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
-            for (;;) {
-                if (!resume && step(e0, e3)) break;
-                resume = false;
-                if (step(e1, e0)) break;
-                if (step(e2, e1)) break;
-                if (step(e3, e2)) break;
+            if constexpr (PAIRS) {
+                for (;;) {
+                    if (step2(e0, e1)) break;
+                    if (step2(e2, e3)) break;
+                }
+            } else {
+                for (;;) {
+                    if (!resume && step(e0, e3)) break;
+                    resume = false;
+                    if (step(e1, e0)) break;
+                    if (step(e2, e1)) break;
+                    if (step(e3, e2)) break;
+                }
             }
             r = outcome(true);
         }
@@ -678,14 +743,14 @@ __device__ __forceinline__ bool light_block(
     return false;
 }
 
-template <int NK, bool ORDERED, typename S, bool ONELINE>
+template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS = false>
 __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (&hrow)[NK], uint32_t ordv,
                                           const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
                                           uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
                                           uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy,
                                           LazyState& lazy, int32_t* j0_out, uint32_t t0)
 {
-    const bool left = light_block<NK, ORDERED, S, ONELINE>(x, hrow, c, cols, L, budget, split_steps, ordv,
+    const bool left = light_block<NK, ORDERED, S, ONELINE, PAIRS>(x, hrow, c, cols, L, budget, split_steps, ordv,
                                                            make_buf(cw + (row >= 0 ? row : 0), row >= 0 ? (uint32_t)c.n : 0u),
                                                            queries + b,
                                                            abandoned + b, lazy, j0_out ? j0_out + b : nullptr, t0);
@@ -1018,8 +1083,9 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         const CodeDesc& c = codes.c[MIXED ? f.ci : 0];
         const S* cols = s_cols + (MIXED ? c.col_base : 0);
         if (HOIST) {
-            light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hrow0, f.ordv, c, cols, L, f.oid, f.row, budget, split_steps,
-                                                  cw, queries, abandoned, ctrs, heavy, lazy, j0_out, t0);
+            light_one<NKMAX, ORDERED, S, ONELINE, !MIXED && NKMAX == 2>(f.x, hrow0, f.ordv, c, cols, L, f.oid, f.row,
+                                                                        budget, split_steps, cw, queries, abandoned,
+                                                                        ctrs, heavy, lazy, j0_out, t0);
         } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
             uint64_t hr[NKMAX];
             load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);

@@ -19,7 +19,7 @@
 #define ORBG_WLEVEL_PACKED 99  // every pattern of logistic weight <= 99 has at most 7 ranks above 8
 #define ORBG_WLEVEL_SCHED 100  // the schedule also takes logistic weight 100 up to its one pattern
                                // with 8 ranks above 8, {9, ..., 16}, the last of its (W, w) class
-#define ORBG_SCHED_PAD 4        // zero batches after a schedule's last batch
+#define ORBG_SCHED_PAD 6        // zero batches after a schedule's last batch
 
 namespace orbg {
 
