@@ -639,19 +639,14 @@ __device__ __forceinline__ bool light_block(
         // entries of steps t + 4 and t + 5: half the scalar bookkeeping per
         // step.  It needs a few more registers, so only the kernels that have
         // them use it (one code, two keys per lane).
-        auto step2 = [&](uint2& ea, uint2& eb) -> bool {
+        auto pair = [&](uint2& ea, uint2& eb, uint64_t& ha, uint64_t& hb) {
             S va, vb;
             entry_syndrome2<S>(L, ea, eb, va, vb);
             // the pair's registers take steps t + 4 and t + 5 once read
             ea = entries(t + 4);
             eb = entries(t + 5);
-            const uint64_t ha = ballot(va == 0);
-            const uint64_t hb = ballot(vb == 0);
-            const uint32_t adv = (ha != 0 || rem == 1) ? 1u : 2u;
-            hits = adv == 1u ? ha : hb;
-            t += adv;
-            rem -= adv;
-            return hits != 0 || rem == 0;
+            ha = ballot(va == 0);
+            hb = ballot(vb == 0);
         };
         // 0 (go on), 1 (hit), 2 (no hit within the budget), 3 (split point).
         // Only the last step of the queries holds lanes past the budget (query
@@ -710,10 +705,24 @@ __device__ __forceinline__ bool light_block(
         if (r == 0) {
             if (!ONELINE) rank_and_tables<NK, S>(x, n, cols, s0, c.rdepth, L);
             if constexpr (PAIRS) {
+                // the loop moves on while neither step hit and more than two
+                // steps are left (one scalar test); the pair that stops it is
+                // settled after it
+                uint64_t ha, hb;
                 for (;;) {
-                    if (step2(e0, e1)) break;
-                    if (step2(e2, e3)) break;
+                    pair(e0, e1, ha, hb);
+                    if ((ha | hb | (rem <= 2u ? 1ull : 0ull)) != 0) break;
+                    t += 2;
+                    rem -= 2;
+                    pair(e2, e3, ha, hb);
+                    if ((ha | hb | (rem <= 2u ? 1ull : 0ull)) != 0) break;
+                    t += 2;
+                    rem -= 2;
                 }
+                const uint32_t adv = (ha != 0 || rem == 1) ? 1u : 2u;
+                hits = adv == 1u ? ha : hb;
+                t += adv;
+                rem -= adv;
             } else {
                 for (;;) {
                     if (!resume && step(e0, e3)) break;
