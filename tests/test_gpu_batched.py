@@ -111,6 +111,37 @@ def test_single_code_naive_launch(gpu_device):
     assert (got[0][sample] == ocw).all() and (got[1][sample].astype(np.uint64) == oq).all()
 
 
+@pytest.mark.parametrize("N", [1, 7, 63, 64, 65, 511, 4097])
+def test_work_slices_cover_every_block_once(gpu_device, N):
+    """The persistent launch deals the blocks to 64 work slices in stripes;
+    batches smaller than the slice count, ragged last stripes, chunks of any size
+    and launches of few or many workgroups must write every block once with the
+    same bits as one one-wave workgroup per block (no work counter).  Outputs
+    start from a sentinel, so a block left out or written from another row
+    shows."""
+    print(f"work slices N={N}", flush=True)
+    H, G = codes.code("bch127_113")
+    from synth import channel
+    llr, _ = channel.awgn_llr(G, N, 4.0, seed=300 + N)
+    x = torch.from_numpy(llr).to(gpu_device)
+    budget = 10 ** 4
+
+    def run(params):
+        cw = torch.full((N, H.shape[1]), 7, dtype=torch.uint8, device=gpu_device)
+        q = torch.full((N,), -1, dtype=torch.int64, device=gpu_device)
+        ab = torch.full((N,), 9, dtype=torch.uint8, device=gpu_device)
+        binding.orbg_decode_ex(H, x, budget, params=params, out=(cw, q, ab))
+        torch.cuda.synchronize()
+        return [v.cpu().numpy() for v in (cw, q, ab)]
+
+    ref = run(binding.LaunchParams(one_block_per_workgroup=1))
+    assert (ref[1] > 0).all() and (ref[0] <= 1).all() and (ref[2] <= 1).all()
+    for wgs, chunk in [(1, 1), (1, 5), (2, 64), (32, 32), (48, 3), (64, 1)]:
+        got = run(binding.LaunchParams(workgroups_per_cu=wgs, chunk=chunk, split_steps=0))
+        for a, b in zip(ref, got):
+            assert (a == b).all(), (wgs, chunk)
+
+
 def test_hip_graph_replay(gpu_device):
     """The mixed decode (counter reset, light pass, heavy pass) captured in a graph:
     every replay, with eager work in between, equals the eager result."""
