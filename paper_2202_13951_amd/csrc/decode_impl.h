@@ -813,11 +813,11 @@ struct ScreenDepth { static constexpr int value = NKMAX >= 16 ? 1 : 16 / NKMAX; 
 // otherwise all blocks use code 0 with rows b * n.  NKMAX: largest keys per
 // lane among the launch's codes.
 //
-// Each wave takes chunks of `chunk` (at most 64) consecutive blocks from XCD
-// slice counters (workgroups are dealt round-robin to the 8 XCDs, so workgroup
-// w works first on slice w % 8 through that slice's counter, then helps the
-// other slices); the counter increment for the next chunk is issued when a
-// chunk starts.  A chunk is decoded in two phases:
+// Each wave takes chunks of `chunk` (at most 64) consecutive blocks from the
+// counters of 64 work slices (striped over the batch; workgroup w works first
+// on slice w % 64, which lies on its own XCD, then helps the other slices;
+// the work cursor below); the counter increment for the next chunk is issued
+// when a chunk starts.  A chunk is decoded in two phases:
 //   1. screening: the rows are read K at a time, all K loads in flight
 //      together, and every block whose base syndrome is zero (query 1 is a
 //      member and comes first) is written out at once;
