@@ -1127,15 +1127,14 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         return;
     }
     if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
-    for (int64_t s = uniform_i64(next_chunk()); s >= 0; s = uniform_i64(next_chunk())) {
-        uint64_t left = screen(s, end);
-        if (left == 0) continue;
-        int64_t b = s + __builtin_ctzll(left);
+    // phase 2 over the blocks left in [base, base + 64) (bit i: block base + i)
+    auto phase2 = [&](uint64_t left, int64_t base) {
+        int64_t b = base + __builtin_ctzll(left);
         left &= left - 1;
         RowFetch<NKMAX> fa, fb;
         fetch(fa, b);
         auto advance = [&](const RowFetch<NKMAX>& cur, RowFetch<NKMAX>& nxt) -> bool {
-            const int64_t bn = left ? s + __builtin_ctzll(left) : -1;
+            const int64_t bn = left ? base + __builtin_ctzll(left) : -1;
             left &= left - 1;
             fetch(nxt, bn);
             decode(cur, b);
@@ -1145,6 +1144,25 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         for (;;) {
             if (!advance(fa, fb)) break;
             if (!advance(fb, fa)) break;
+        }
+    };
+    // One code, two keys per lane, not 1-line: a chunk is worked through K
+    // blocks at a time, one screening group and then its phase 2, so the
+    // phase-2 rows are read again while the screening's reads of them still sit
+    // in L2 (with the whole chunk screened first, most of those reads miss it),
+    // the counter still taking one increment per chunk.  The other kernels
+    // screen whole chunks: there the extra loop state spilled registers to
+    // scratch.
+    constexpr bool BY_GROUP = NKMAX == 2 && !ONELINE && !MIXED;
+    for (int64_t s = uniform_i64(next_chunk()); s >= 0; s = uniform_i64(next_chunk())) {
+        if constexpr (BY_GROUP) {
+            for (int64_t g = s; g < end; g += K) {
+                const uint64_t left = screen(g, (g + K < end) ? g + K : end);
+                if (left != 0) phase2(left, g);
+            }
+        } else {
+            const uint64_t left = screen(s, end);
+            if (left != 0) phase2(left, s);
         }
     }
 }
