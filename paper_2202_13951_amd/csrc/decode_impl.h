@@ -843,7 +843,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
              const uint8_t* __restrict__ order, uint8_t* __restrict__ cw, uint64_t* __restrict__ queries,
              uint8_t* __restrict__ abandoned, unsigned long long* __restrict__ ctrs, int64_t* __restrict__ heavy,
              int chunk, int32_t* __restrict__ j0_out, int64_t row_limit, const int64_t* __restrict__ ids,
-             uint32_t t0, int naive)
+             uint32_t t0, int naive, uint32_t fixed)
 {
     // dynamic LDS (sized at launch): the rows of the launch's codes (sum of
     // m x nk words), then their columns (sum of n entries)
@@ -894,7 +894,16 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     int slice = home;
     int64_t len = uniform_i64(slice_len(home)), end = 0;
     unsigned long long* ctr = ctrs + ORBG_CTR_SLICE(home);
-    unsigned long long pend = 0;
+    // The first chunk of each of the first `fixed` workgroups of a slice
+    // (those resident from the start) is fixed, with no increment: workgroup w
+    // is the (w / S)-th of its slice and takes that chunk of it, and the
+    // counters start past those chunks (set so before the launch).  Otherwise
+    // every wave would start by queueing on its slice's counter, the last of a
+    // slice's waves ~0.1 us x their number later.  Later workgroups (they start
+    // only as others end) claim their first chunk as usual.
+    const uint32_t rank = blockIdx.x / ORBG_SLICES;
+    unsigned long long pend = (unsigned long long)rank * (unsigned long long)chunk;
+    if (rank >= fixed && lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
     // The slice to move to when the current one is drained, or -1 when all are:
     // lane x reads slice x's counter (one coherent load, no increment), and
     // since a counter only grows, a slice seen drained stays drained.  The pick
@@ -1126,7 +1135,6 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         }
         return;
     }
-    if (lane == 0) pend = atomicAdd(ctr, (unsigned long long)chunk);
     // phase 2 over the blocks left in [base, base + 64) (bit i: block base + i)
     auto phase2 = [&](uint64_t left, int64_t base) {
         int64_t b = base + __builtin_ctzll(left);
@@ -1289,9 +1297,13 @@ heavy_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     }
 }
 
-static __global__ void reset_counters_kernel(unsigned long long* c)
+// Counters before a light pass: zero, but each slice counter past the slice's
+// fixed first chunks (slice_start blocks).
+static __global__ void reset_counters_kernel(unsigned long long* c, unsigned long long slice_start)
 {
     for (int i = threadIdx.x; i < ORBG_CTR_WORDS; i += blockDim.x) c[i] = 0ull;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ORBG_SLICES; i += blockDim.x) c[ORBG_CTR_SLICE(i)] = slice_start;
 }
 
 template <int NKMAX, bool ORDERED, typename S, bool MIXED, bool ONELINE>
@@ -1303,9 +1315,20 @@ static void launch_light(const DecodeArgs& a, int64_t wgs, int chunk, uint32_t s
         ncols = e > ncols ? e : ncols;
     }
     const size_t lds = (size_t)a.codes.rwords * sizeof(uint64_t) + ncols * sizeof(S);
+    uint32_t fixed = 0;
+    if (!a.p.naive) {
+        // workgroups per slice resident from the start take fixed first chunks
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE>,
+                                                         ORBG_WAVE, lds) != hipSuccess)
+            per_cu = 0;
+        const int64_t resident = (int64_t)per_cu * a.cus;
+        fixed = (uint32_t)((resident < wgs ? resident : wgs) / ORBG_SLICES);
+        reset_counters_kernel<<<1, 64, 0, stream>>>(a.ctrs, (unsigned long long)fixed * (unsigned long long)chunk);
+    }
     light_kernel<NKMAX, ORDERED, S, MIXED, ONELINE><<<(unsigned)wgs, ORBG_WAVE, lds, stream>>>(
         a.codes, a.block_code, a.row_off, a.llr, a.nblocks, a.budget, split, a.order, a.cw, a.queries,
-        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit, a.ids, a.skip0 ? 1u : 0u, a.p.naive);
+        a.abandoned, a.ctrs, a.heavy, chunk, a.j0, a.row_limit, a.ids, a.skip0 ? 1u : 0u, a.p.naive, fixed);
 }
 
 template <int NKMAX, typename S, bool MIXED, int G, bool ONELINE>
@@ -1337,7 +1360,6 @@ static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
     }
     chunk = chunk > 64 ? 64 : chunk;                    // a chunk's blocks fit one 64-bit mask
     const uint32_t split = (a.heavy != nullptr && a.p.split_steps > 0) ? (uint32_t)a.p.split_steps : 0u;
-    reset_counters_kernel<<<1, 64, 0, stream>>>(a.ctrs);
     launch_light<NKMAX, ORDERED, S, MIXED, ONELINE>(a, wgs, chunk, split, stream);
     if (split && !a.list_only) {
         if (a.p.heavy_waves >= 16) launch_heavy_g<NKMAX, S, MIXED, 16, ONELINE>(a, split, stream);
