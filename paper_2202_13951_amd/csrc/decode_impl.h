@@ -871,15 +871,15 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     // g % S, so every slice holds the same mix of the batch (a batch laid out by
     // channel condition still gives slices of equal cost, which drain
     // together).  Z is a whole number of chunks, up to ORBG_STRIPE of them, and
-    // small enough that each slice gets about 8 stripes or more.  Workgroup w starts on slice w % S, which lies on its
-    // own XCD (workgroups are dealt round-robin to the 8 XCDs).  A slice's
-    // counter counts the blocks claimed, `chunk` at a time (chunks never cross a
-    // stripe, Z being a multiple of the chunk); `pend` (lane 0) receives the
-    // next chunk's counter value, claimed when a chunk starts.  Increments of
-    // one counter queue one behind another (of the order of 0.1 us each), so
-    // many slices keep few waves on each counter: with one per XCD, the one
-    // increment every wave makes cost about 0.1 ms per launch, whatever the
-    // number of blocks.
+    // small enough that each slice gets about 8 stripes or more.  Workgroup w
+    // starts on slice w % S, which lies on its own XCD (workgroups are dealt
+    // round-robin to the 8 XCDs).  A slice's counter counts the blocks claimed,
+    // `chunk` at a time (chunks never cross a stripe, Z being a multiple of the
+    // chunk); `pend` (lane 0) receives the next chunk's counter value, claimed
+    // when a chunk starts.  Increments of one counter queue one behind another
+    // (of the order of 0.1 us each), so many slices keep few waves on each
+    // counter: with one slice per XCD, the increments that find slices drained
+    // cost about 0.1 ms per launch, whatever the number of blocks.
     const int64_t zc = nblocks / ((int64_t)ORBG_SLICES * chunk * 8);
     const int64_t Z = (int64_t)chunk * (zc < 1 ? 1 : zc > ORBG_STRIPE ? ORBG_STRIPE : zc);
     const int64_t nstripes = (nblocks + Z - 1) / Z;
