@@ -30,6 +30,8 @@
 // With a batch order (learned proposal) step t < 64 tests batch order[t] of the
 // schedule instead of batch t; from step 64 on the plain order continues.
 #pragma once
+#include <type_traits>
+
 #include "orbg_device.h"
 #include "orbg_internal.h"
 #include "orbg_kernels.h"
@@ -89,6 +91,55 @@ __device__ __forceinline__ void load_row_buf(buf_t r, float (&x)[NK])
 #pragma unroll
     for (int j = 0; j < NK; ++j)
         x[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (j * ORBG_WAVE + lane_id()) * 4, 0, 0));
+}
+
+// Lane offsets of a kernel's row and result accesses, made once per kernel so
+// that every access shares the same registers.  l[j] / c[j]: byte offset of
+// element j * 64 + lane in an LLR row / a codeword row, or ORBG_PAST for a
+// lane past the code's length (one code per launch) — an offset beyond every
+// descriptor's size, so the lane reads 0 and its store is dropped;  r: 0 on
+// lane 0 and ORBG_PAST elsewhere (a block's query count and flag).
+#define ORBG_PAST 0x40000000u
+template <int NK>
+struct LaneOffs {
+    uint32_t l[NK];
+    uint32_t c[NK];
+    uint32_t r;
+};
+
+// n_mask: the length past which lanes are cut (any value >= 64 NK cuts none).
+template <int NK>
+__device__ __forceinline__ LaneOffs<NK> lane_offsets(int n_mask)
+{
+    LaneOffs<NK> o;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const uint32_t i = (uint32_t)(j * ORBG_WAVE + lane_id());
+        const bool in = i < (uint32_t)n_mask;
+        o.l[j] = in ? i * 4u : ORBG_PAST;
+        o.c[j] = in ? i : ORBG_PAST;
+    }
+    o.r = lane_id() == 0 ? 0u : ORBG_PAST;
+    return o;
+}
+
+// Kernels without a kernel-wide set compute lane offsets in place from the lane
+// (none cut).
+struct NoOffs {};
+template <class LO>
+constexpr bool has_offs() { return !std::is_same<LO, NoOffs>::value; }
+
+// A row at byte offset `soff` from the descriptor's base, read with the
+// kernel's lane offsets.
+template <int NK, class LO>
+__device__ __forceinline__ void load_row_buf(buf_t r, float (&x)[NK], const LO& lo, uint32_t soff = 0)
+{
+    if constexpr (!has_offs<LO>()) {
+        load_row_buf<NK>(r, x);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NK; ++j) x[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lo.l[j], soff, 0));
+    }
 }
 
 // Read-only tables read with wave-uniform indices: through the constant
@@ -158,14 +209,18 @@ __device__ __forceinline__ S hard_decision(const float (&x)[NK], int n, const ui
                                            bool (&ybit)[NK])
 {
     const int lane = lane_id();
+    // the parity of a sum of popcounts is the parity of the XOR of the words:
+    // the masked words are folded first (a AND b XOR c in one three-input bit
+    // operation, truth table 0x6a), one popcount at the end
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
         ybit[j] = (j * ORBG_WAVE + lane < n) && (x[j] > 0.0f);
         const uint64_t y = ballot(ybit[j]);
-        acc += __popc((uint32_t)hrow[j] & (uint32_t)y) + __popc((uint32_t)(hrow[j] >> 32) & (uint32_t)(y >> 32));
+        acc = __builtin_amdgcn_bitop3_b32((uint32_t)hrow[j], (uint32_t)y, acc, 0x6a);
+        acc = __builtin_amdgcn_bitop3_b32((uint32_t)(hrow[j] >> 32), (uint32_t)(y >> 32), acc, 0x6a);
     }
-    return (S)ballot((acc & 1u) != 0u);
+    return (S)ballot((__popc(acc) & 1u) != 0u);
 }
 
 template <int NK>
@@ -480,9 +535,9 @@ __device__ __forceinline__ void entry_syndrome2(const BlockLds<S>& L, uint2 ea, 
 // through the row's buffer descriptor (lanes past n store nothing).  The
 // received position of each flipped rank is wave-uniform; the lane holding it
 // toggles its bit.
-template <int NK, typename S>
+template <int NK, typename S, class LO>
 __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const BlockLds<S>& L, uint32_t win_lo,
-                                               uint32_t win_hi, buf_t cw_row)
+                                               uint32_t win_hi, buf_t cw_row, const LO& lo)
 {
     const int lane = lane_id();
     bool bit[NK];
@@ -501,8 +556,12 @@ __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const Blo
         if (r != 0) flip(r);
     }
 #pragma unroll
-    for (int j = 0; j < NK; ++j)
-        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, j * ORBG_WAVE + lane, 0, 0);
+    for (int j = 0; j < NK; ++j) {
+        if constexpr (has_offs<LO>())
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, lo.c[j], 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, j * ORBG_WAVE + lane, 0, 0);
+    }
 }
 
 // Query count and abandon flag of one block: lane 0's stores are the only ones
@@ -513,6 +572,14 @@ __device__ __forceinline__ void write_result(uint64_t* q_out, uint8_t* ab_out, u
     const u32x2_t v = {q, 0u};
     __builtin_amdgcn_raw_buffer_store_b64(v, make_buf(q_out, 8), lane * 8, 0, 0);
     __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(abandon ? 1 : 0), make_buf(ab_out, 1), lane, 0, 0);
+}
+
+// The same with the kernel's lane offset r (0 on lane 0 only).
+__device__ __forceinline__ void write_result(uint64_t* q_out, uint8_t* ab_out, uint32_t q, bool abandon, uint32_t r)
+{
+    const u32x2_t v = {q, 0u};
+    __builtin_amdgcn_raw_buffer_store_b64(v, make_buf(q_out, 8), r, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(abandon ? 1 : 0), make_buf(ab_out, 1), r, 0, 0);
 }
 
 // Schedule of a 1-line block with fitted offset j0 (offsets above the code's
@@ -534,12 +601,12 @@ __device__ __forceinline__ void write_offset(int32_t* j0_out, int j0)
 // (then nothing is written but the 1-line offset).  ONELINE: the block's fitted
 // offset (written to j0_out when that is not null) picks its schedule.  PAIRS:
 // the search tests two steps per branch.
-template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS>
+template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS, class LO>
 __device__ __forceinline__ bool light_block(
     const float (&x)[NK], const uint64_t (&hrow)[NK], const CodeDesc& c, const S* __restrict__ cols,
     BlockLds<S>& L, uint32_t budget, uint32_t split_steps, uint32_t ordv, buf_t cw_row,
     uint64_t* __restrict__ q_out, uint8_t* __restrict__ ab_out, LazyState& lazy, int32_t* __restrict__ j0_out,
-    uint32_t t0 = 0)
+    const LO& lo, uint32_t t0 = 0)
 {
     const int lane = lane_id();
     const int n = c.n;
@@ -746,23 +813,26 @@ __device__ __forceinline__ bool light_block(
         found = (r == 1);
     }
 
-    write_codeword<NK, S>(ybit, L, win_lo, win_hi, cw_row);
-    write_result(q_out, ab_out, found ? q : budget, !found);
+    write_codeword<NK, S>(ybit, L, win_lo, win_hi, cw_row, lo);
+    if constexpr (has_offs<LO>())
+        write_result(q_out, ab_out, found ? q : budget, !found, lo.r);
+    else
+        write_result(q_out, ab_out, found ? q : budget, !found);
     wave_lds_sync();
     return false;
 }
 
-template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS = false>
+template <int NK, bool ORDERED, typename S, bool ONELINE, bool PAIRS = false, class LO = NoOffs>
 __device__ __forceinline__ void light_one(const float (&x)[NK], const uint64_t (&hrow)[NK], uint32_t ordv,
                                           const CodeDesc& c, const S* cols, BlockLds<S>& L, int64_t b, int64_t row,
                                           uint32_t budget, uint32_t split_steps, uint8_t* cw, uint64_t* queries,
                                           uint8_t* abandoned, unsigned long long* ctrs, int64_t* heavy,
-                                          LazyState& lazy, int32_t* j0_out, uint32_t t0)
+                                          LazyState& lazy, int32_t* j0_out, uint32_t t0, const LO& lo)
 {
-    const bool left = light_block<NK, ORDERED, S, ONELINE, PAIRS>(x, hrow, c, cols, L, budget, split_steps, ordv,
-                                                           make_buf(cw + (row >= 0 ? row : 0), row >= 0 ? (uint32_t)c.n : 0u),
-                                                           queries + b,
-                                                           abandoned + b, lazy, j0_out ? j0_out + b : nullptr, t0);
+    const bool left = light_block<NK, ORDERED, S, ONELINE, PAIRS, LO>(
+        x, hrow, c, cols, L, budget, split_steps, ordv,
+        make_buf(cw + (row >= 0 ? row : 0), row >= 0 ? (uint32_t)c.n : 0u), queries + b, abandoned + b, lazy,
+        j0_out ? j0_out + b : nullptr, lo, t0);
     if (left && lane_id() == 0) {
         const unsigned long long slot = atomicAdd(ctrs + ORBG_CTR_HEAVY_COUNT, 1ull);
         heavy[slot] = b;
@@ -865,6 +935,15 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
     constexpr bool HOIST = !MIXED && NKMAX <= 4;
     uint64_t hrow0[NKMAX];
     if (HOIST) load_hrows<NKMAX>(s_rows, codes.c[0].m, hrow0);
+    // One code with two keys per lane (the kernel of the widest use): every row
+    // and result access takes its lane offsets from one set made here, lanes
+    // past n cut, and the screening reads a group's rows through one
+    // descriptor.  The other kernels compute lane offsets in place (a kernel-wide
+    // set spilled registers there).
+    constexpr bool FLAT = !MIXED && NKMAX == 2;
+    using LO = typename std::conditional<FLAT, LaneOffs<NKMAX>, NoOffs>::type;
+    LO lo;
+    if constexpr (FLAT) lo = lane_offsets<NKMAX>(codes.c[0].n);
 
     // Work cursor (wave-uniform).  The blocks are dealt to ORBG_SLICES slices in
     // stripes of Z blocks: stripe g (blocks [g Z, (g + 1) Z)) goes to slice
@@ -981,6 +1060,71 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
             // cost more vector instructions than the screening itself.
             const CodeDesc& c = codes.c[0];
             const int n = c.n;
+            if constexpr (FLAT) {
+                if (ids == nullptr) {
+                    // Blocks in launch order: a group's rows lie back to back, so
+                    // one descriptor covers them all (and one each the group's
+                    // codewords, query counts and flags) and a row is picked by a
+                    // scalar offset, the only per-row address arithmetic.  Lanes
+                    // past n hold offsets beyond every descriptor's size (lo), so
+                    // they read 0 and their stores are dropped whether or not the
+                    // scalar offset enters the hardware's range check; rows past
+                    // the group's count take scalar offset 0 (a row of the group,
+                    // read and never screened).
+                    const uint32_t n4 = (uint32_t)n * 4u;
+                    for (int64_t g = s; g < e; g += K) {
+                        float xs[K][NKMAX];
+                        uint32_t first[K];
+                        uint32_t cnt = uniform_u32((uint32_t)((e - g) < K ? (e - g) : K));
+                        asm volatile("" : "+s"(cnt));     // compared as a 32-bit scalar below
+                        const buf_t lb = make_buf(llr + g * n, cnt * n4);
+                        const buf_t ob = make_buf(ORDERED ? order + g * 64 : order, ORDERED ? cnt * 64u : 0u);
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk) {
+                            const bool ok = (uint32_t)kk < cnt;
+                            load_row_buf<NKMAX>(lb, xs[kk], lo, ok ? (uint32_t)kk * n4 : 0u);
+                            first[kk] = ORDERED ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(
+                                                      ob, lo.r, ok ? (uint32_t)kk * 64u : 0u, 0)
+                                                : 0u;
+                        }
+                        int64_t g2 = g;
+                        uint32_t cnt2 = cnt;
+                        asm volatile("" : "+s"(g2), "+s"(cnt2));
+                        const buf_t cb = make_buf(cw + g2 * n, cnt2 * (uint32_t)n);
+                        const buf_t qb = make_buf(queries + g2, cnt2 * 8u);
+                        const buf_t ab = make_buf(abandoned + g2, cnt2);
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk) {
+                            if ((uint32_t)kk < cnt2) {
+                                uint64_t hr[NKMAX];
+                                if (HOIST) {
+#pragma unroll
+                                    for (int j = 0; j < NKMAX; ++j) hr[j] = hrow0[j];
+                                } else {
+                                    load_hrows<NKMAX>(s_rows, c.m, hr);
+                                }
+                                bool yb[NKMAX];
+                                const S s0 = hard_decision<NKMAX, S>(xs[kk], n, hr, yb);
+                                const bool done = s0 == 0 && (!ORDERED || uniform_u32(first[kk]) == 0u) &&
+                                                  !(ONELINE && j0_out != nullptr);
+                                if (done) {
+#pragma unroll
+                                    for (int j = 0; j < NKMAX; ++j)
+                                        __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cb, lo.c[j],
+                                                                             (uint32_t)kk * (uint32_t)n, 0);
+                                    const u32x2_t q1 = {1u, 0u};
+                                    __builtin_amdgcn_raw_buffer_store_b64(q1, qb, lo.r, (uint32_t)kk * 8u, 0);
+                                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)0, ab, lo.r, (uint32_t)kk, 0);
+                                } else {
+                                    left |= 1ull << (g2 + kk - s);
+                                }
+                            }
+                        }
+                    }
+                    return left;
+                }
+            }
+            // A block list: each row's output index is read from the list.
             auto out_index = [&](int64_t b) -> int64_t { return ids ? scalar_load_i64(ids, b) : b; };
             for (int64_t g = s; g < e; g += K) {
                 float xs[K][NKMAX];
@@ -990,7 +1134,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                 for (int kk = 0; kk < K; ++kk) {
                     const bool ok = (uint32_t)kk < cnt;
                     const int64_t oid = ok ? out_index(g + kk) : 0;
-                    load_row_buf<NKMAX>(make_buf(llr + oid * n, ok ? (uint32_t)n * 4u : 0u), xs[kk]);
+                    load_row_buf<NKMAX>(make_buf(llr + oid * n, ok ? (uint32_t)n * 4u : 0u), xs[kk], lo);
                     first[kk] = ORDERED ? (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(
                                               make_buf(order + (ok ? g + kk : 0) * 64, ok ? 1u : 0u), 0, 0, 0)
                                         : 0u;
@@ -1016,10 +1160,17 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
                             const int64_t oid = out_index(g2 + kk);
                             const buf_t cwr = make_buf(cw + oid * n, (uint32_t)n);
 #pragma unroll
-                            for (int j = 0; j < NKMAX; ++j)
-                                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, j * ORBG_WAVE + lane,
-                                                                     0, 0);
-                            write_result(queries + oid, abandoned + oid, 1u, false);
+                            for (int j = 0; j < NKMAX; ++j) {
+                                if constexpr (FLAT)
+                                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr, lo.c[j], 0, 0);
+                                else
+                                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(yb[j] ? 1 : 0), cwr,
+                                                                         j * ORBG_WAVE + lane, 0, 0);
+                            }
+                            if constexpr (FLAT)
+                                write_result(queries + oid, abandoned + oid, 1u, false, lo.r);
+                            else
+                                write_result(queries + oid, abandoned + oid, 1u, false);
                         } else {
                             left |= 1ull << (g2 + kk - s);
                         }
@@ -1094,7 +1245,7 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         f.oid = oid;
         const bool rv = b >= 0 && row >= 0;
         const uint32_t bytes = rv ? (uint32_t)codes.c[ci].n * 4u : 0u;
-        load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), bytes), f.x);
+        load_row_buf<NKMAX>(make_buf(llr + (rv ? row : 0), bytes), f.x, lo);
         f.ordv = ORDERED ? load_order_buf(make_buf(order + (b >= 0 ? b : 0) * 64, b >= 0 ? 64u : 0u)) : 0u;
     };
     auto decode = [&](const RowFetch<NKMAX>& f, int64_t b) {
@@ -1103,25 +1254,25 @@ light_kernel(CodeTable codes, const uint8_t* __restrict__ block_code, const int6
         if (HOIST) {
             light_one<NKMAX, ORDERED, S, ONELINE, !MIXED && NKMAX == 2>(f.x, hrow0, f.ordv, c, cols, L, f.oid, f.row,
                                                                         budget, split_steps, cw, queries, abandoned,
-                                                                        ctrs, heavy, lazy, j0_out, t0);
+                                                                        ctrs, heavy, lazy, j0_out, t0, lo);
         } else if (!MIXED || NKMAX == 1 || c.nk == NKMAX) {
             uint64_t hr[NKMAX];
             load_hrows<NKMAX>(s_rows + c.row_base, c.m, hr);
             light_one<NKMAX, ORDERED, S, ONELINE>(f.x, hr, f.ordv, c, cols, L, f.oid, f.row, budget, split_steps, cw,
-                                                  queries, abandoned, ctrs, heavy, lazy, j0_out, t0);
+                                                  queries, abandoned, ctrs, heavy, lazy, j0_out, t0, lo);
         } else if (c.nk == 1) {
             uint64_t hr[1];
             load_hrows<1>(s_rows + c.row_base, c.m, hr);
             light_one<1, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[1]>(f.x), hr, f.ordv, c, cols, L, f.oid,
                                               f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy, lazy,
-                                              j0_out, t0);
+                                              j0_out, t0, NoOffs{});
         } else {
             constexpr int K2 = NKMAX >= 2 ? 2 : 1;
             uint64_t hr[K2];
             load_hrows<K2>(s_rows + c.row_base, c.m, hr);
             light_one<K2, ORDERED, S, ONELINE>(*reinterpret_cast<const float(*)[K2]>(f.x), hr, f.ordv, c, cols, L,
                                                f.oid, f.row, budget, split_steps, cw, queries, abandoned, ctrs, heavy,
-                                               lazy, j0_out, t0);
+                                               lazy, j0_out, t0, NoOffs{});
         }
     };
 
@@ -1244,7 +1395,7 @@ __device__ __forceinline__ void heavy_block(const CodeDesc& c, const float* __re
             win_lo = uniform_u32(w.x);
             win_hi = uniform_u32(w.y);
         }
-        write_codeword<NK, S>(ybit, L, win_lo, win_hi, make_buf(cw_row, row_ok ? (uint32_t)n : 0u));
+        write_codeword<NK, S>(ybit, L, win_lo, win_hi, make_buf(cw_row, row_ok ? (uint32_t)n : 0u), NoOffs{});
         write_result(q_out, ab_out, found ? q : budget, !found);
     }
     __syncthreads();
