@@ -408,10 +408,12 @@ struct LazyState {
     uint32_t tries;    // blocks that needed a search
 };
 
-// Tables for the first batch after rank_first: h[r], pi[r] for r <= ra and T.
+// Tables for the first batch after rank_first, in two parts.  first_ranks:
+// h[r], pi[r] for r <= ra, and hs[e] = h_{e+1} for the ranks the low-rank
+// table covers (read from the lanes that hold them).
 template <typename S>
-__device__ __forceinline__ void first_tables(uint32_t idx1, int ra, const S* __restrict__ cols, S s0,
-                                             BlockLds<S>& L)
+__device__ __forceinline__ void first_ranks(uint32_t idx1, int ra, const S* __restrict__ cols, BlockLds<S>& L,
+                                            S (&hs)[ORBG_LOW_RANKS])
 {
     const int lane = lane_id();
     const S col = cols[lane < ra ? idx1 : 0u];
@@ -421,9 +423,15 @@ __device__ __forceinline__ void first_tables(uint32_t idx1, int ra, const S* __r
         L.pi[lane + 1] = (uint16_t)idx1;
     }
     if (lane == 0) { L.h[0] = 0; L.pi[0] = 0; }
-    S hs[ORBG_LOW_RANKS];
 #pragma unroll
     for (int e = 0; e < ORBG_LOW_RANKS; ++e) hs[e] = readlane_s<S>(hv, e);
+}
+
+// low_table: T[m] = s0 XOR (XOR of h_r over the bits r - 1 of m), m < 256.
+template <typename S>
+__device__ __forceinline__ void low_table(const S (&hs)[ORBG_LOW_RANKS], S s0, BlockLds<S>& L)
+{
+    const int lane = lane_id();
     S a = s0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) a ^= ((lane >> b) & 1) ? hs[b] : (S)0;
@@ -533,21 +541,22 @@ __device__ __forceinline__ void entry_syndrome2(const BlockLds<S>& L, uint2 ea, 
 
 // Step 5: the hard decision with the winning entry's ranks flipped, stored
 // through the row's buffer descriptor (lanes past n store nothing).  The
-// received position of each flipped rank is wave-uniform; the lane holding it
-// toggles its bit.
+// received position of each flipped rank is wave-uniform: it goes into a
+// wave-uniform mask of the positions to flip (one 64-bit word per key), which
+// every lane applies once at the end.
 template <int NK, typename S, class LO>
 __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const BlockLds<S>& L, uint32_t win_lo,
                                                uint32_t win_hi, buf_t cw_row, const LO& lo)
 {
     const int lane = lane_id();
-    bool bit[NK];
+    uint64_t fm[NK];
 #pragma unroll
-    for (int j = 0; j < NK; ++j) bit[j] = ybit[j];
+    for (int j = 0; j < NK; ++j) fm[j] = 0;
     auto flip = [&](uint32_t r) {
         const uint32_t p = uniform_u32(L.pi[r]);
+        const uint64_t b = 1ull << (p & 63u);
 #pragma unroll
-        for (int j = 0; j < NK; ++j)
-            if ((p >> 6) == (uint32_t)j) bit[j] ^= (uint32_t)lane == (p & 63u);
+        for (int j = 0; j < NK; ++j) fm[j] ^= (p >> 6) == (uint32_t)j ? b : 0ull;
     };
     for (uint32_t low = win_lo & 0xffu; low != 0; low &= low - 1) flip((uint32_t)__builtin_ctz(low) + 1u);
 #pragma unroll
@@ -557,10 +566,11 @@ __device__ __forceinline__ void write_codeword(const bool (&ybit)[NK], const Blo
     }
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
+        const uint32_t v = (uint32_t)(ybit[j] ? 1 : 0) ^ (uint32_t)((fm[j] >> lane) & 1ull);
         if constexpr (has_offs<LO>())
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, lo.c[j], 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, cw_row, lo.c[j], 0, 0);
         else
-            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bit[j] ? 1 : 0), cw_row, j * ORBG_WAVE + lane, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, cw_row, j * ORBG_WAVE + lane, 0, 0);
     }
 }
 
@@ -749,22 +759,34 @@ __device__ __forceinline__ bool light_block(
         lazy.tries = uniform_u32(lazy.tries + 1u);
         if (!ORDERED && !ONELINE && (lazy.score >= 160u || (lazy.tries & 7u) == 0u || split_steps == 1u) &&
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
-            first_tables<S>(idx1, c.rdepth0, cols, s0, L);
-            if constexpr (PAIRS) {
-                // step 0 alone; the entries move down one step, the next load
-                // taking step 4
-                const uint2 e4 = entries(t + 4);
-                hits = ballot(entry_syndrome<S>(L, e0) == 0);
-                ++t;
-                --rem;
-                r = outcome(hits != 0 || rem == 0);
-                e0 = e1;
-                e1 = e2;
-                e2 = e3;
-                e3 = e4;
+            S hs[ORBG_LOW_RANKS];
+            first_ranks<S>(idx1, c.rdepth0, cols, L, hs);
+            if (t0 == 0u && lim >= 3u && (s0 == hs[0] || s0 == hs[1])) {
+                // queries 2 and 3 of the plain order are {1} and {2} (logistic
+                // weights 1 and 2): a block they decide needs no table and no step
+                found = true;
+                q = s0 == hs[0] ? 2u : 3u;
+                win_lo = s0 == hs[0] ? 1u : 2u;       // mask of ranks 1..8: rank 1 or rank 2
+                r = 1;
+                wave_lds_sync();
             } else {
-                r = outcome(step(e0, e3));
-                resume = true;
+                low_table<S>(hs, s0, L);
+                if constexpr (PAIRS) {
+                    // step 0 alone; the entries move down one step, the next
+                    // load taking step 4
+                    const uint2 e4 = entries(t + 4);
+                    hits = ballot(entry_syndrome<S>(L, e0) == 0);
+                    ++t;
+                    --rem;
+                    r = outcome(hits != 0 || rem == 0);
+                    e0 = e1;
+                    e1 = e2;
+                    e2 = e3;
+                    e3 = e4;
+                } else {
+                    r = outcome(step(e0, e3));
+                    resume = true;
+                }
             }
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
