@@ -797,14 +797,16 @@ __device__ __forceinline__ bool light_block(
                 // the loop moves on while neither step hit and more than two
                 // steps are left (one scalar test); the pair that stops it is
                 // settled after it
+                // (rem - 3) >> 31 is rem <= 2 (rem < 2^31) as a bit: computed
+                // without a compare, the test stays on the scalar unit
                 uint64_t ha, hb;
                 for (;;) {
                     pair(e0, e1, ha, hb);
-                    if ((ha | hb | (rem <= 2u ? 1ull : 0ull)) != 0) break;
+                    if ((ha | hb | (uint64_t)((rem - 3u) >> 31)) != 0) break;
                     t += 2;
                     rem -= 2;
                     pair(e2, e3, ha, hb);
-                    if ((ha | hb | (rem <= 2u ? 1ull : 0ull)) != 0) break;
+                    if ((ha | hb | (uint64_t)((rem - 3u) >> 31)) != 0) break;
                     t += 2;
                     rem -= 2;
                 }
