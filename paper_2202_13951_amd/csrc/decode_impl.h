@@ -761,32 +761,22 @@ __device__ __forceinline__ bool light_block(
             rank_first<NK, S>(x, n, c.rdepth0, lazy.tau, L, idx1)) {
             S hs[ORBG_LOW_RANKS];
             first_ranks<S>(idx1, c.rdepth0, cols, L, hs);
-            if (t0 == 0u && lim >= 3u && (s0 == hs[0] || s0 == hs[1])) {
-                // queries 2 and 3 of the plain order are {1} and {2} (logistic
-                // weights 1 and 2): a block they decide needs no table and no step
-                found = true;
-                q = s0 == hs[0] ? 2u : 3u;
-                win_lo = s0 == hs[0] ? 1u : 2u;       // mask of ranks 1..8: rank 1 or rank 2
-                r = 1;
-                wave_lds_sync();
+            low_table<S>(hs, s0, L);
+            if constexpr (PAIRS) {
+                // step 0 alone; the entries move down one step, the next load
+                // taking step 4
+                const uint2 e4 = entries(t + 4);
+                hits = ballot(entry_syndrome<S>(L, e0) == 0);
+                ++t;
+                --rem;
+                r = outcome(hits != 0 || rem == 0);
+                e0 = e1;
+                e1 = e2;
+                e2 = e3;
+                e3 = e4;
             } else {
-                low_table<S>(hs, s0, L);
-                if constexpr (PAIRS) {
-                    // step 0 alone; the entries move down one step, the next
-                    // load taking step 4
-                    const uint2 e4 = entries(t + 4);
-                    hits = ballot(entry_syndrome<S>(L, e0) == 0);
-                    ++t;
-                    --rem;
-                    r = outcome(hits != 0 || rem == 0);
-                    e0 = e1;
-                    e1 = e2;
-                    e2 = e3;
-                    e3 = e4;
-                } else {
-                    r = outcome(step(e0, e3));
-                    resume = true;
-                }
+                r = outcome(step(e0, e3));
+                resume = true;
             }
             lazy.score = uniform_u32(lazy.score - (lazy.score >> 3) + (r != 0 ? 32u : 0u));
         }
