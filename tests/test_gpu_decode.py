@@ -78,6 +78,36 @@ def test_shapes_and_ragged_lengths(gpu_device, n, k):
     _assert_same(_gpu_decode(H, llr, budget, gpu_device), O.decode(H, llr, budget, THREADS), f"n={n}")
 
 
+@pytest.mark.parametrize("n,k,N", [(127, 113, 1001), (100, 88, 777), (65, 52, 515)])
+def test_rows_stay_inside_their_views(gpu_device, n, k, N):
+    """Each block's outputs are written inside their own bytes only, and each
+    block is decoded from its own row: the LLRs and the outputs are views one
+    row into larger buffers whose first and last rows hold other data (LLRs of
+    a large magnitude, so a row read from the wrong offset changes the
+    results; sentinel bytes, which a stray store would change).  Several
+    launch shapes, partial screening groups among them."""
+    print(f"row views n={n} k={k} N={N}", flush=True)
+    H = codes.bch_H(127, 113) if n == 127 else codes.rlc_H(n, k, seed=n * 11 + k)
+    G = codes.generator_matrix(H)
+    llr, _ = channel.awgn_llr(G, N, 4.0, seed=n + N)
+    budget = 10 ** 4
+    want = O.decode(H, llr, budget, THREADS)
+    big = np.full((N + 2, n), -40.0, dtype=np.float32)
+    big[1:N + 1] = llr
+    xb = torch.from_numpy(big).to(gpu_device)
+    for wgs, chunk in [(0, 0), (1, 5), (32, 32), (48, 3)]:
+        cwb = torch.full((N + 2, n), 7, dtype=torch.uint8, device=gpu_device)
+        qb = torch.full((N + 2,), -1, dtype=torch.int64, device=gpu_device)
+        abb = torch.full((N + 2,), 9, dtype=torch.uint8, device=gpu_device)
+        params = binding.LaunchParams(workgroups_per_cu=wgs, chunk=chunk, split_steps=0) if wgs else None
+        binding.orbg_decode_ex(H, xb[1:N + 1], budget, params=params, out=(cwb[1:N + 1], qb[1:N + 1], abb[1:N + 1]))
+        torch.cuda.synchronize()
+        cw, q, ab = cwb.cpu().numpy(), qb.cpu().numpy(), abb.cpu().numpy()
+        for r in (0, N + 1):
+            assert (cw[r] == 7).all() and q[r] == -1 and ab[r] == 9, (wgs, chunk, r)
+        _assert_same((cw[1:N + 1], q[1:N + 1].astype(np.uint64), ab[1:N + 1]), want, f"n={n} shape {wgs}/{chunk}")
+
+
 def test_budget_edges_and_abandon(gpu_device):
     print("budget edges", flush=True)
     H = codes.rlc_H(40, 20, seed=5)                      # 20 parity bits: pure noise abandons
