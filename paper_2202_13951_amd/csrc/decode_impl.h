@@ -1519,9 +1519,13 @@ static hipError_t launch_all(const DecodeArgs& a, hipStream_t stream)
     int chunk = a.p.chunk;
     if (chunk <= 0) {
         // about 4 chunks per wave: a counter increment is a round trip to L2,
-        // so chunks stay as long as the balance at the end allows
-        const int64_t c = a.nblocks / (wgs * 4);
-        chunk = (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
+        // so chunks stay as long as the balance at the end allows; a whole
+        // number of screening groups when that is one or more (a chunk's last
+        // group is not cut short)
+        constexpr int K = ScreenDepth<NKMAX>::value;
+        int64_t c = a.nblocks / (wgs * 4);
+        c = c < 1 ? 1 : (c > 64 ? 64 : c);
+        chunk = (int)(c >= K ? c - c % K : c);
     }
     chunk = chunk > 64 ? 64 : chunk;                    // a chunk's blocks fit one 64-bit mask
     const uint32_t split = (a.heavy != nullptr && a.p.split_steps > 0) ? (uint32_t)a.p.split_steps : 0u;
