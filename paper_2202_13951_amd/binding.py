@@ -122,28 +122,31 @@ def _host_H(H) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(H), dtype=np.uint8)
 
 
-def _need(cond: bool, msg: str):
-    """Argument check that survives python -O (raises ValueError)."""
+def _need(cond: bool, msg):
+    """Argument check that survives python -O (raises ValueError).  msg: the
+    message, or a function that makes it (formatted only when the check fails,
+    so a passing check costs no string formatting)."""
     if not cond:
-        raise ValueError(msg)
+        raise ValueError(msg() if callable(msg) else msg)
 
 
 def _tensor_spec(t, name: str, dtype, shape=None, ndim=None):
     """t must be a contiguous torch tensor of this dtype (and shape / rank)."""
     import torch
-    _need(isinstance(t, torch.Tensor), f"{name} must be a torch tensor")
-    _need(t.dtype == dtype, f"{name} must be {dtype} (got {t.dtype})")
+    _need(isinstance(t, torch.Tensor), lambda: f"{name} must be a torch tensor")
+    _need(t.dtype == dtype, lambda: f"{name} must be {dtype} (got {t.dtype})")
     if ndim is not None:
-        _need(t.dim() == ndim, f"{name} must have {ndim} dimension(s)")
+        _need(t.dim() == ndim, lambda: f"{name} must have {ndim} dimension(s)")
     if shape is not None:
-        _need(tuple(t.shape) == tuple(shape), f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
-    _need(t.is_contiguous(), f"{name} must be contiguous")
+        _need(tuple(t.shape) == tuple(shape),
+              lambda: f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    _need(t.is_contiguous(), lambda: f"{name} must be contiguous")
 
 
 def _on_device(t, name: str, device=None):
-    _need(t.is_cuda, f"{name} must be on a CUDA device")
+    _need(t.is_cuda, lambda: f"{name} must be on a CUDA device")
     if device is not None:
-        _need(t.device == device, f"{name} is on {t.device}, expected {device}")
+        _need(t.device == device, lambda: f"{name} is on {t.device}, expected {device}")
 
 
 def _dev_tensor(t, name: str, dtype, shape=None, device=None, ndim=None):
